@@ -1,0 +1,375 @@
+"""Pins of the CPU oracle against things other than itself (no GPU needed).
+
+Each test names the passage of the paper it checks and the independent fact that
+pins it: brute force, a library routine, an exact enumeration, or an identity.
+"""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.spatial.distance as ssd
+
+import oracle
+
+
+# ---------------------------------------------------------------- bins (Algorithm 1)
+def test_bins_partition_exhaustive():
+    """Contiguous balanced bins: every row in exactly one bin, sizes differ by <= 1,
+    and the bin of row j equals floor(((j+1)L - 1)/N) (an independent closed form)."""
+    for N in range(1, 90):
+        for L in range(1, N + 1):
+            starts = [oracle.bin_start(b, N, L) for b in range(L + 1)]
+            assert starts[0] == 0 and starts[-1] == N
+            sizes = np.diff(starts)
+            assert sizes.min() >= 1 and sizes.max() - sizes.min() <= 1
+            for j in range(N):
+                b = oracle.bin_of(j, N, L)
+                assert starts[b] <= j < starts[b + 1]
+                assert b == ((j + 1) * L - 1) // N
+
+
+def test_bins_power_of_two_is_shift_right():
+    """With N = L * 2^W the balanced partition is Algorithm 1's ShiftRight(j, W)."""
+    for W in range(0, 6):
+        for L in (1, 3, 8, 64):
+            N = L << W
+            for j in range(N):
+                assert oracle.bin_of(j, N, L) == j >> W
+
+
+def _brute_bins(S, L, minimize):
+    M, N = S.shape
+    V = np.empty((M, L))
+    A = np.empty((M, L), np.int64)
+    for b in range(L):
+        j0, j1 = oracle.bin_start(b, N, L), oracle.bin_start(b + 1, N, L)
+        blk = S[:, j0:j1]
+        a = np.argmin(blk, axis=1) if minimize else np.argmax(blk, axis=1)  # first occurrence
+        V[:, b] = blk[np.arange(M), a]
+        A[:, b] = j0 + a
+    return V, A
+
+
+@pytest.mark.parametrize("minimize", [False, True])
+def test_partial_reduce_vs_bruteforce_with_ties(minimize):
+    """Algorithm 1 (strict compare, increasing j) == per-bin argmax with first-occurrence
+    ties, on small-integer scores full of ties, for every L <= N."""
+    rng = np.random.default_rng(7)
+    for N in range(1, 13):
+        S = rng.integers(-3, 4, size=(5, N)).astype(np.float64)
+        for L in range(1, N + 1):
+            V, A = oracle.partial_reduce(S, L, minimize)
+            Vb, Ab = _brute_bins(S, L, minimize)
+            np.testing.assert_array_equal(V, Vb)
+            np.testing.assert_array_equal(A, Ab)
+
+
+def test_search_invariants():
+    """Winners lie in their bin, equal the bin's true best, ties go to the lowest row;
+    the runner-up is the best of the other rows."""
+    rng = np.random.default_rng(3)
+    Q = rng.integers(-2, 3, size=(6, 4)).astype(np.float32)
+    X = rng.integers(-2, 3, size=(50, 4)).astype(np.float32)
+    for metric in ("mips", "l2", "cosine"):
+        S, _ = oracle.scores(Q, X, metric)
+        mn = oracle.minimize_for(metric)
+        for L in (1, 2, 7, 16, 50):
+            r = oracle.search(Q, X, metric, L, 1, bins=True)
+            for i in range(6):
+                for b in range(L):
+                    j0, j1 = oracle.bin_start(b, 50, L), oracle.bin_start(b + 1, 50, L)
+                    a = r["bin_i"][i, b]
+                    assert j0 <= a < j1
+                    blk = S[i, j0:j1]
+                    best = blk.min() if mn else blk.max()
+                    assert r["bin_v"][i, b] == best
+                    assert a == j0 + int(np.flatnonzero(blk == best)[0])
+                    others = np.delete(blk, a - j0)
+                    if others.size:
+                        assert r["bin2_v"][i, b] == (others.min() if mn else others.max())
+
+
+# ---------------------------------------------------------------- scores (Sec. 2, appendix)
+def test_scores_vs_library():
+    """MIPS == numpy's matrix product; cosine == 1 - scipy's cosine distance; zero norm -> 0."""
+    rng = np.random.default_rng(1)
+    Q = rng.standard_normal((7, 33)).astype(np.float32)
+    X = rng.standard_normal((40, 33)).astype(np.float32)
+    X[5] = 0
+    S, _ = oracle.scores(Q, X, "mips")
+    np.testing.assert_allclose(S, Q.astype(np.float64) @ X.astype(np.float64).T, rtol=1e-12, atol=1e-12)
+    C, _ = oracle.scores(Q, X, "cosine")
+    for i in range(7):
+        for j in range(40):
+            if j == 5:
+                assert C[i, j] == 0.0
+            else:
+                ref = 1.0 - ssd.cosine(Q[i].astype(np.float64), X[j].astype(np.float64))
+                assert abs(C[i, j] - ref) < 1e-12
+
+
+def test_relaxed_l2_identity_and_ranking():
+    """Appendix (eq. l2-suboptimal, eq. l2final): 2*(|x|^2/2 - <q,x>) + |q|^2 = |q - x|^2,
+    so ranking by the relaxed score equals ranking by the Euclidean distance (integer data:
+    exact in FP64)."""
+    rng = np.random.default_rng(2)
+    Q = rng.integers(0, 256, size=(9, 16)).astype(np.float32)
+    X = rng.integers(0, 256, size=(300, 16)).astype(np.float32)
+    S, _ = oracle.scores(Q, X, "l2")
+    d2 = ((Q[:, None, :].astype(np.float64) - X[None, :, :].astype(np.float64)) ** 2).sum(-1)
+    qq = (Q.astype(np.float64) ** 2).sum(1)[:, None]
+    np.testing.assert_array_equal(2 * S + qq, d2)
+    for i in range(9):
+        o1 = np.lexsort((np.arange(300), S[i]))
+        o2 = np.lexsort((np.arange(300), ssd.cdist(Q[i:i + 1], X, "euclidean")[0]))
+        np.testing.assert_array_equal(o1, o2)
+
+
+# ---------------------------------------------------------------- top-K (ExactRescoring)
+@pytest.mark.parametrize("metric", ["mips", "l2", "cosine"])
+def test_L_equals_N_is_exact_knn(metric):
+    """With one row per bin every row is a winner, so the result is the exact K-NN
+    (eq. 1 / eq. 2), checked against numpy's stable sort of the FP64 scores."""
+    rng = np.random.default_rng(4)
+    Q = rng.integers(-3, 4, size=(5, 6)).astype(np.float32)
+    X = rng.integers(-3, 4, size=(37, 6)).astype(np.float32)
+    S, _ = oracle.scores(Q, X, metric)
+    mn = oracle.minimize_for(metric)
+    r = oracle.search(Q, X, metric, 37, 9, exact=True)
+    for i in range(5):
+        key = S[i] if mn else -S[i]
+        order = np.lexsort((np.arange(37), key))[:9]
+        np.testing.assert_array_equal(r["top_i"][i], order)
+        np.testing.assert_array_equal(r["ex_i"][i], order)
+
+
+def test_K1_exact_for_any_L_and_L1_is_argmax():
+    """The global best is always some bin's winner: K = 1 is exact for every L; L = 1, K = 1
+    is numpy's argmax (first occurrence)."""
+    rng = np.random.default_rng(5)
+    Q = rng.standard_normal((4, 8)).astype(np.float32)
+    X = rng.standard_normal((200, 8)).astype(np.float32)
+    S, _ = oracle.scores(Q, X, "mips")
+    for L in (1, 2, 3, 17, 64, 200):
+        r = oracle.search(Q, X, "mips", L, 1, exact=True)
+        np.testing.assert_array_equal(r["top_i"][:, 0], np.argmax(S, axis=1))
+        np.testing.assert_array_equal(r["ex_i"][:, 0], np.argmax(S, axis=1))
+
+
+def test_nested_bins_recall_monotone():
+    """Refining every bin into c pieces (L' = c L, N divisible) can only keep more
+    true neighbours: per-query recall is non-decreasing in c."""
+    rng = np.random.default_rng(6)
+    Q = rng.standard_normal((16, 8)).astype(np.float32)
+    X = rng.standard_normal((960, 8)).astype(np.float32)
+    prev = None
+    for L in (15, 30, 60, 120, 240, 960):
+        r = oracle.search(Q, X, "mips", L, 10, exact=True)
+        rec = oracle.recall(r["top_i"], r["ex_i"])
+        if prev is not None:
+            assert np.all(rec >= prev - 1e-12)
+        prev = rec
+    assert np.all(prev == 1.0)
+
+
+# ---------------------------------------------------------------- recall model (Sec. 4.1)
+def _enumerated_recall(N, L, K):
+    """Exact E[recall] by running the oracle on every placement of the K true neighbours."""
+    tot = Fraction(0)
+    cnt = 0
+    Q = np.ones((1, 1), np.float32)
+    for P in itertools.combinations(range(N), K):
+        x = np.arange(N, dtype=np.float32)[:, None] * 0.0 - np.arange(N, dtype=np.float32)[:, None]
+        for rank, p in enumerate(P):
+            x[p, 0] = 1000.0 - rank  # the K best rows, all distinct
+        r = oracle.search(Q, x, "mips", L, K, exact=True)
+        tot += Fraction(len(set(r["top_i"][0]) & set(r["ex_i"][0])), K)
+        cnt += 1
+    return tot / cnt
+
+
+@pytest.mark.parametrize("N,L,K,expect", [
+    (8, 4, 2, Fraction(13, 14)),
+    (12, 4, 3, Fraction(136, 165)),
+    (12, 5, 4, Fraction(177, 220)),
+    (9, 9, 4, Fraction(1)),
+    (10, 3, 3, None),
+    (11, 4, 2, None),
+])
+def test_recall_expectation_by_enumeration(N, L, K, expect):
+    """Sec. 4.1: recall = (#bins holding a true neighbour)/K.  The closed form
+    (1/K) sum_b [1 - C(N-B_b,K)/C(N,K)] equals exhaustive enumeration of all placements
+    through the oracle's own search, and is >= the paper's bound ((L-1)/L)^(K-1)."""
+    enum = _enumerated_recall(N, L, K)
+    closed = oracle.recall_exact_balanced(N, L, K, exact_fraction=True)
+    assert enum == closed
+    if expect is not None:
+        assert closed == expect
+    assert float(closed) >= oracle.recall_bound_paper(K, L) - 1e-15
+    assert abs(float(closed) - oracle.recall_exact_balanced(N, L, K)) < 1e-12
+
+
+def test_recall_monte_carlo_at_mips_small_shape():
+    """N = 65536, L = 2048, K = 10 with i.i.d. scores (row order independent of the query):
+    the mean recall over 3200 queries lies within 5 sigma of the exact balanced-bin
+    expectation and above the paper's bound."""
+    N, L, K = 65536, 2048, 10
+    exact = oracle.recall_exact_balanced(N, L, K)
+    bound = oracle.recall_bound_paper(K, L)
+    assert abs(exact - 0.997874) < 1e-6 and abs(bound - 0.995614) < 1e-6
+    rng = np.random.default_rng(11)
+    recs = []
+    for _ in range(50):
+        S = rng.standard_normal((64, N))
+        V, A = oracle.partial_reduce(S, L, False)
+        _, top = oracle.topk_pairs(V, A, K, False)
+        truth = np.argsort(-S, axis=1, kind="stable")[:, :K]
+        recs.append(oracle.recall(top, truth))
+    recs = np.concatenate(recs)
+    sigma = recs.std() / math.sqrt(recs.size)
+    assert abs(recs.mean() - exact) < 5 * sigma + 1e-12
+    assert recs.mean() > bound
+
+
+def test_bins_for_recall():
+    """eq. l:approx: K = 10, r = 0.95 -> L >= 1/(1 - 0.95^(1/9)) = 175.97 -> 176; the
+    first-order form (K-1)/(1-r) gives 180; the result is the smallest L meeting eq. recall."""
+    assert oracle.bins_for_recall(10, 0.95) == 176
+    assert abs(oracle.bins_for_recall_approx(10, 0.95) - 180.0) < 1e-9
+    for K in (2, 5, 10, 64, 100):
+        for r in (0.5, 0.9, 0.95, 0.99):
+            L = oracle.bins_for_recall(K, r)
+            assert oracle.recall_bound_paper(K, L) >= r
+            if L > K:
+                assert oracle.recall_bound_paper(K, L - 1) < r
+    assert oracle.bins_for_recall(1, 0.99) == 1
+    assert oracle.bins_for_recall(10, 0.95, N=100) == 100
+    assert oracle.bins_for_recall(64, 0.95) == 1229 and oracle.bins_for_recall(100, 0.95) == 1931
+
+
+# ---------------------------------------------------------------- quantisers
+def test_bf16_round_vs_torch():
+    """RNE to BF16 == torch's float32 -> bfloat16 conversion (a library routine)."""
+    import torch
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.standard_normal(200000).astype(np.float32) * 100,
+                        np.array([0.0, -0.0, 1.0, 1.00390625, 1.01171875, 255.0, 256.0, 257.0, -3e-39],
+                                 np.float32)])
+    mid = (np.arange(1, 4096, dtype=np.uint32) << 16 | np.uint32(0x8000)) + np.uint32(0x3F800000)
+    x = np.concatenate([x, mid.view(np.float32)])  # exact ties
+    v, codes = oracle.bf16_round(x)
+    t = torch.from_numpy(x).to(torch.bfloat16)
+    np.testing.assert_array_equal(codes, t.view(torch.int16).numpy().view(np.uint16))
+    np.testing.assert_array_equal(v, t.float().numpy())
+    ints = np.arange(0, 256, dtype=np.float32)
+    np.testing.assert_array_equal(oracle.bf16_round(ints)[0], ints)  # 0..255 exact in BF16
+
+
+def test_fp8_table_and_round_vs_torch():
+    """E4M3 (OCP): 127 non-negative finite values, max 448, min subnormal 2^-9, min normal
+    2^-6; RNE agrees with torch's float8_e4m3fn conversion on in-range values; saturation."""
+    import torch
+    tab = oracle.fp8_e4m3_table()
+    assert tab.size == 127 and tab[-1] == 448.0 and tab[1] == 2.0 ** -9 and tab[8] == 2.0 ** -6
+    assert np.all(np.diff(tab) > 0)
+    rng = np.random.default_rng(9)
+    y = np.concatenate([rng.uniform(-448, 448, 100000), rng.standard_normal(100000) * 0.01,
+                        (tab[:-1] + tab[1:]) / 2, -(tab[:-1] + tab[1:]) / 2, tab, -tab])
+    y = y.astype(np.float32).astype(np.float64)
+    vals, codes = oracle.fp8_round(y)
+    t = torch.from_numpy(y.astype(np.float32)).to(torch.float8_e4m3fn)
+    np.testing.assert_array_equal(codes, t.view(torch.uint8).numpy())
+    np.testing.assert_array_equal(vals, t.float().numpy().astype(np.float64))
+    v2, c2 = oracle.fp8_round(np.array([500.0, -1e6, 449.0]))
+    assert list(v2) == [448.0, -448.0, 448.0] and list(c2) == [0x7E, 0xFE, 0x7E]
+
+
+def test_fp8_row_exponent_minimal():
+    """The row exponent is the smallest e with amax <= 448 * 2^e."""
+    rng = np.random.default_rng(10)
+    amax = np.abs(rng.standard_normal(5000)) * 10.0 ** rng.uniform(-8, 8, 5000)
+    amax = np.concatenate([amax, [448.0, 448.0 * 2 ** -3, 449.0, 1.0, 0.0]])
+    e = oracle.fp8_row_exponent(amax)
+    nz = amax > 0
+    assert np.all(amax[nz] <= 448.0 * 2.0 ** e[nz])
+    assert np.all(amax[nz] > 448.0 * 2.0 ** (e[nz] - 1))
+    assert e[-1] == 0 and e[-5] == 0 and e[-3] == 1 and e[-2] == -8
+
+
+def test_normalize_rows_f32():
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((100, 100)).astype(np.float32)
+    X[3] = 0
+    Xn = oracle.normalize_rows_f32(X)
+    n = np.sqrt((Xn.astype(np.float64) ** 2).sum(1))
+    assert np.all(np.abs(n[np.arange(100) != 3] - 1) < 1e-6) and n[3] == 0
+
+
+# ---------------------------------------------------------------- backward reference
+@pytest.mark.parametrize("metric", ["mips", "l2", "cosine"])
+def test_backward_vs_finite_differences(metric):
+    """Dense FP64 gradient of a softmax cross-entropy over the retrieved scores (selection
+    frozen) against central finite differences, at Q = 8, N = 4096, D = 16, K = 64, L = 1024."""
+    from paper_2206_14286_amd import datagen
+    M, N, D, K, L = 8, 4096, 16, 64, 1024
+    Q = datagen.normal(M, D, 101)
+    X = datagen.normal(N, D, 100)
+    t = datagen.targets(M, K, 102)
+    r = oracle.search(Q, X, metric, L, K)
+    a = r["top_i"]
+
+    def loss(Qm, Xm):
+        s, _ = oracle.pair_scores(Qm, Xm, metric, np.repeat(np.arange(M), K), a.ravel())
+        s = s.reshape(M, K)
+        z = s - s.max(1, keepdims=True)
+        lse = np.log(np.exp(z).sum(1))
+        return float(np.mean(lse - z[np.arange(M), t]))
+
+    s, _ = oracle.pair_scores(Q, X, metric, np.repeat(np.arange(M), K), a.ravel())
+    s = s.reshape(M, K)
+    p = np.exp(s - s.max(1, keepdims=True))
+    p /= p.sum(1, keepdims=True)
+    g = p.copy()
+    g[np.arange(M), t] -= 1.0
+    g /= M
+    dQ, dX = oracle.backward(g, a, Q, X, metric)
+    h = 1e-3  # FP32 inputs: perturb in FP64 through a float64 copy
+    Qd, Xd = Q.astype(np.float64), X.astype(np.float64)
+    rng = np.random.default_rng(0)
+    coords = [("q", i, d) for i in range(M) for d in range(D)]
+    rows = np.unique(a.ravel())
+    coords += [("x", int(j), int(d)) for j in rng.choice(rows, 40, replace=False) for d in rng.choice(D, 3)]
+    coords += [("x", int(j), 0) for j in np.setdiff1d(np.arange(N), rows)[:5]]
+
+    def loss64(Qm, Xm):
+        return loss_fd(Qm, Xm)
+
+    def loss_fd(Qm, Xm):
+        qi = np.repeat(np.arange(M), K)
+        xj = a.ravel()
+        qv, xv = Qm[qi], Xm[xj]
+        dot = (qv * xv).sum(1)
+        if metric == "mips":
+            s = dot
+        elif metric == "l2":
+            s = 0.5 * (xv * xv).sum(1) - dot
+        else:
+            s = dot / np.sqrt((qv * qv).sum(1) * (xv * xv).sum(1))
+        s = s.reshape(M, K)
+        z = s - s.max(1, keepdims=True)
+        return float(np.mean(np.log(np.exp(z).sum(1)) - z[np.arange(M), t]))
+
+    assert abs(loss_fd(Qd, Xd) - loss(Q, X)) < 1e-9
+    for kind, i, d in coords:
+        A_ = Qd if kind == "q" else Xd
+        old = A_[i, d]
+        A_[i, d] = old + h
+        lp = loss64(Qd, Xd)
+        A_[i, d] = old - h
+        lm = loss64(Qd, Xd)
+        A_[i, d] = old
+        fd = (lp - lm) / (2 * h)
+        an = dQ[i, d] if kind == "q" else dX[i, d]
+        assert abs(fd - an) <= 1e-6 + 1e-5 * abs(an), (kind, i, d, fd, an)
