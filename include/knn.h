@@ -1,0 +1,208 @@
+/*
+ * knn.h -- C ABI of the MI355X (gfx950) approximate K-NN library.
+ *
+ * The library implements the two-kernel search of "TPU-KNN: K Nearest
+ * Neighbor Search at Peak FLOP/s" (Chern et al., 2022):
+ *   PartialReduce (Sec. 4, Algorithm 1): the query-database distance GEMM fused
+ *     with a reduction that keeps, for each query, the best score and its row
+ *     index in each of L bins, so the M x N score matrix never reaches memory;
+ *   ExactRescoring (Sec. 4): the exact top-K over the M x L bin winners.
+ * Scores (Sec. 2 and the appendix on Euclidean search):
+ *   KNN_MIPS    <q, x>                      maximised (eq. 2)
+ *   KNN_L2      |x|^2 / 2 - <q, x>          minimised (eq. l2final); returned as is,
+ *                                           so |q - x|^2 = 2 * value + |q|^2
+ *   KNN_COSINE  <q, x> / (|q| |x|)          maximised; cosine distance = 1 - value;
+ *                                           a zero-norm row or query scores 0
+ * Bins are contiguous balanced row ranges: bin b holds rows
+ *   [floor(b N / L), floor((b + 1) N / L)),
+ * which is Algorithm 1's ShiftRight(j, W) when N = L * 2^W.  Inside a bin the
+ * lowest row index wins ties; results are ordered best first, ties by lower index.
+ * Expected recall (Sec. 4.1, eq. recall) is at least ((L-1)/L)^(K-1).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named Q, X, out_*, bins_*, g, idx, dQ, dX are DEVICE pointers,
+ *     owned by the caller, row-major and contiguous.  FP32 data is 4-byte aligned,
+ *     BF16 data 2-byte aligned.  Handles (knn_db, knn_plan) are owned by the library.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it
+ *     and the call returns without synchronising, except where noted.
+ *   - Arguments are checked before anything is enqueued.  On error the call returns
+ *     a non-zero knn_status, knn_last_error() describes it (per thread), nothing is
+ *     enqueued and the outputs are untouched.  No C++ exception crosses the ABI.
+ *   - Sizes: 1 <= K <= L <= N < 2^31, 1 <= D <= 256, M >= 0 (M = 0 is a no-op).
+ *     Row indices are int32.
+ *   - Inputs with NaN or infinity give unspecified results (they are not scanned).
+ */
+#ifndef KNN_MI355X_H
+#define KNN_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KNN_OK = 0,
+  KNN_ERR_INVALID = 1,     /* bad argument: size, pointer, enum, handle */
+  KNN_ERR_UNSUPPORTED = 2, /* valid but not implemented (e.g. D > 256) */
+  KNN_ERR_OOM = 3,         /* device or host allocation failed */
+  KNN_ERR_HIP = 4          /* a HIP runtime call or kernel launch failed */
+} knn_status;
+
+typedef enum { KNN_MIPS = 0, KNN_L2 = 1, KNN_COSINE = 2 } knn_metric;
+
+/* Element types.  KNN_F32 and KNN_BF16 may be input types; all three may be the
+ * compute type of the distance GEMM (FP32 accumulation in every case).
+ * KNN_FP8_E4M3 is the OCP E4M3 format (max 448) with one power-of-two scale per
+ * row: x ~ code(x * 2^-e) * 2^e, e the smallest integer with max|x| <= 448 * 2^e. */
+typedef enum { KNN_F32 = 0, KNN_BF16 = 1, KNN_FP8_E4M3 = 2 } knn_dtype;
+
+typedef struct knn_db knn_db;     /* a prepared database (opaque) */
+typedef struct knn_plan knn_plan; /* a batched search plan (opaque) */
+
+/* ------------------------------------------------------------------ helpers (host only) */
+
+/* Smallest L with ((L-1)/L)^(K-1) >= r (Sec. 4.1, eq. l:approx, exact inverse),
+ * clamped to [K, N]; K == 1 gives 1.  Returns -1 for K < 1, N < 1 or r outside (0, 1). */
+int64_t knn_bins_for_recall(int32_t K, double recall_target, int64_t N);
+
+/* ((L-1)/L)^(K-1) (Sec. 4.1, eq. recall); NaN for K < 1 or L < 1. */
+double knn_expected_recall_bound(int32_t K, int64_t L);
+
+/* First row of bin b: floor(b N / L).  -1 for invalid arguments. */
+int64_t knn_bin_start(int64_t b, int64_t N, int64_t L);
+
+/* Static description of a status code. */
+const char* knn_status_string(int32_t status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* knn_last_error(void);
+
+/* Number of HIP devices visible (0 without a GPU); never fails. */
+int32_t knn_device_count(void);
+
+/* ------------------------------------------------------------------ database preparation */
+
+/* Prepare a database once for many searches (the paper passes the L2 half norms
+ * precomputed, appendix on Euclidean search): for cosine the rows are
+ * unit-normalised in FP32; rows are then converted to `compute` (FP32 copy, BF16
+ * round-to-nearest-even, or per-row scaled FP8 E4M3), zero-padded to the MFMA
+ * depth and stored in the layout the distance kernel streams; L2 also stores
+ * |x~|^2 / 2 of the converted rows.  For the FP32 rerank of low-precision
+ * searches the handle keeps X's device pointer: X must stay valid and unchanged
+ * for the life of the handle.
+ *   X        device, N x D, type in_dtype (KNN_F32 or KNN_BF16)
+ *   out      receives the handle; free it with knn_db_destroy.
+ * Allocates device memory (hipMalloc); synchronises `stream` before returning. */
+knn_status knn_db_create(const void* X, int32_t in_dtype, int64_t N, int32_t D, int32_t metric,
+                         int32_t compute, void* stream, knn_db** out);
+
+knn_status knn_db_destroy(knn_db* db);
+
+/* Copy the prepared rows back to HOST buffers in plain row-major form, for tests:
+ *   codes      N x D elements of the compute type (float, uint16 BF16 bits, uint8 E4M3 codes)
+ *   exponents  N int32 row exponents e (FP8 only; may be NULL)
+ *   half_norms N floats |x~|^2 / 2 (L2 only; may be NULL).
+ * Synchronises `stream`. */
+knn_status knn_db_export(const knn_db* db, void* codes, int32_t* exponents, float* half_norms,
+                         void* stream);
+
+/* ------------------------------------------------------------------ search */
+
+/* The plain FP32 search: Q (M x D) against X (N x D), both FP32 device arrays.
+ * L <= 0 chooses L = knn_bins_for_recall(K, 0.95, N).  Writes the best K per query,
+ * best first: out_val FP32[M x K], out_idx int32[M x K].  Allocates its temporary
+ * buffers stream-ordered (hipMallocAsync) and prepares X on every call. */
+knn_status knn_search(const float* Q, int64_t M, const float* X, int64_t N, int32_t D, int32_t K,
+                      int64_t L, int32_t metric, float* out_val, int32_t* out_idx, void* stream);
+
+/* Search a prepared database.
+ *   Q          device, M x D, type q_dtype (KNN_F32 or KNN_BF16)
+ *   L          bins (L <= 0: knn_bins_for_recall(K, 0.95, N))
+ *   rerank_k   0: return the top-K of the bin winners by the compute-type score;
+ *              K..L: take the best rerank_k bin winners by the compute-type score,
+ *              rescore them in FP32 from the original Q and X rows, return the best K
+ *              (the precision form of the search: BF16 / FP8 GEMM + FP32 rerank)
+ *   out_val/out_idx  M x K, best first (scores are FP32 rescored ones when reranking)
+ *   bins_val/bins_idx optional M x L bin winners (Algorithm 1's V and A, compute-type
+ *              scores in the metric's own sign); NULL to skip (the `aggregate_to_topk`
+ *              option of the paper's op corresponds to out_* being used).
+ * Temporary buffers are allocated stream-ordered. */
+knn_status knn_db_search(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, int32_t K, int64_t L,
+                         int32_t rerank_k, float* out_val, int32_t* out_idx, float* bins_val,
+                         int32_t* bins_idx, void* stream);
+
+/* The two steps of a search exposed on their own, for callers that reuse prepared
+ * queries and for timing the distance kernel alone.
+ * knn_query_buffer_bytes: size of the device buffer knn_query_prepare fills for M queries.
+ * knn_query_prepare: queries -> the layout the distance kernel reads (same conversion as
+ *   the database: cosine normalisation, compute type, padding).  qbuf is a device buffer
+ *   of at least knn_query_buffer_bytes(db, M) bytes, owned by the caller.
+ * knn_partial_reduce: PartialReduce alone (Sec. 4, Algorithm 1): the M x L bin winners
+ *   (bins_val FP32, bins_idx int32, device, row-major), compute-type scores in the
+ *   metric's own sign; no top-K (the `aggregate_to_topk = False` form of the paper's op). */
+size_t knn_query_buffer_bytes(const knn_db* db, int64_t M);
+knn_status knn_query_prepare(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, void* qbuf,
+                             size_t qbuf_bytes, void* stream);
+knn_status knn_partial_reduce(const knn_db* db, const void* qbuf, int64_t M, int64_t L, float* bins_val,
+                              int32_t* bins_idx, void* stream);
+
+/* ------------------------------------------------------------------ batched search */
+
+/* One query batch of a batched plan: M_b queries (device, M_b x D_db, FP32 or BF16
+ * as q_dtype) against database `db` (an index into the plan's database list),
+ * K_b results written to out_val/out_idx (device, M_b x K_b). */
+typedef struct {
+  const void* Q;
+  int64_t M;
+  int32_t db;
+  int32_t K;
+  float* out_val;
+  int32_t* out_idx;
+} knn_batch;
+
+/* Build a plan for `nb` uneven query batches against `ndb` prepared databases.
+ * All buffers the search needs are allocated here, so knn_search_batched allocates
+ * nothing and may be captured into a hipGraph.  The batch pointers are bound now:
+ * replays read the queries from, and write the results to, the same buffers.
+ * For each database the plan picks L >= knn_bins_for_recall(max K, recall_target, N)
+ * and the kernel tiling; with tune != 0 it times candidates on `stream` with
+ * hipEvents (the autotuner) and caches the choice in the JSON file `cache_path`
+ * (NULL: no cache); with tune == 0 it uses a fixed heuristic.
+ * Synchronises `stream`. */
+knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn_batch* batches, int32_t nb,
+                           int32_t q_dtype, double recall_target, int32_t tune, const char* cache_path,
+                           void* stream, knn_plan** out);
+
+/* Run every batch of the plan: one query-preparation launch, one persistent
+ * distance + bin-reduce launch over a device work list that covers all batches
+ * and databases, and one top-K launch.  No allocation, no host synchronisation. */
+knn_status knn_search_batched(knn_plan* plan, void* stream);
+
+/* The plan's per-database choices: L, query-block width and rows per work item
+ * (host arrays of length ndb; any may be NULL). */
+knn_status knn_plan_info(const knn_plan* plan, int64_t* L, int32_t* qblock, int64_t* chunk_rows);
+
+knn_status knn_plan_destroy(knn_plan* plan);
+
+/* ------------------------------------------------------------------ backward */
+
+/* Gradient of sum_{i,k} g[i,k] * score(q_i, x_{idx[i,k]}) with the selection held
+ * fixed (the retrieved indices are constants):
+ *   MIPS:    dQ_i = sum_k g_ik x_j           dX_j += sum g_ik q_i
+ *   L2:      dQ_i = -sum_k g_ik x_j          dX_j += sum g_ik (x_j - q_i)
+ *   COSINE:  dQ_i = sum_k g_ik (x_j/(|q||x|) - c q_i/|q|^2)
+ *            dX_j += sum g_ik (q_i/(|q||x|) - c x_j/|x|^2),   c the cosine score.
+ *   g    device FP32 M x K;  idx device int32 M x K (entries outside [0, N) are skipped)
+ *   Q, X device, in_dtype (KNN_F32 or KNN_BF16), M x D and N x D
+ *   dQ   device FP32 M x D, overwritten
+ *   dX   device FP32 N x D, ACCUMULATED with FP32 atomics (zero it first); NULL to skip. */
+knn_status knn_backward(const float* g, const int32_t* idx, const void* Q, const void* X, int32_t in_dtype,
+                        int64_t M, int64_t N, int32_t D, int32_t K, int32_t metric, float* dQ, float* dX,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KNN_MI355X_H */

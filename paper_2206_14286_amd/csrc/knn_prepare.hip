@@ -1,0 +1,160 @@
+// knn_prepare.hip -- row preparation for the distance kernel.
+//
+// One thread per row.  For cosine the row is unit-normalised in FP32 (|x|^2
+// summed in dimension order with one rounding per product and per sum, correctly
+// rounded square root and divisions), which makes cosine search an inner-product
+// search (Sec. 2: MIPS equals cosine search on l2-normalised data).  The row is
+// then converted to the compute type, zero-padded to the MFMA depth (the paper
+// pads GloVe's D = 100 to 128, appendix "Benchmark details") and scattered into
+// the fragment layout described in knn_internal.h.  For L2 the aux block gets
+// -|x~|^2/2 of the converted row: the distance kernel starts its accumulators
+// from it, so <q,x> - |x|^2/2 (the negated relaxed distance of eq. l2final)
+// comes out of the matrix unit with no extra per-score instruction.
+#include "knn_common.cuh"
+
+namespace knn {
+
+namespace {
+
+struct RowView {
+  const void* src;
+  int dt;
+  int64_t base;
+  int D;
+  bool valid, cosine;
+  float nrm;
+  __device__ __forceinline__ float get(int d) const {
+    if (!valid || d >= D) return 0.f;
+    float x = load_elem(src, dt, base + d);
+    if (!cosine) return x;
+    return nrm > 0.f ? x / nrm : 0.f;  // correctly rounded division (HIP default)
+  }
+};
+
+// source row r (valid if r < rows) -> destination row dst of `tiles`
+template <int CDT>
+__device__ void prepare_row(const void* src, int in_dt, int64_t r, int64_t rows, int64_t dst, int D, int ng,
+                            int metric, bool database, unsigned char* tiles, float* orig_half_norm,
+                            float* orig_rnorm) {
+  // one rounding per product and per sum: no fused multiply-add in this function
+#pragma clang fp contract(off)
+  const bool valid = src != nullptr && r < rows;
+  const int64_t base = r * (int64_t)D;
+  float ss = 0.f;
+  if (valid)
+    for (int d = 0; d < D; ++d) {
+      float x = load_elem(src, in_dt, base + d);
+      ss = ss + x * x;
+    }
+  const float nrm = sqrtf(ss);  // correctly rounded square root (HIP default)
+  if (valid && orig_half_norm) orig_half_norm[r] = 0.5f * ss;
+  if (valid && orig_rnorm) orig_rnorm[r] = nrm > 0.f ? 1.f / nrm : 0.f;
+  RowView v{src, in_dt, base, D, valid, metric == MET_COSINE, nrm};
+
+  int e = 0;
+  if (CDT == DT_FP8) {
+    float amax = 0.f;
+    for (int d = 0; d < D; ++d) amax = fmaxf(amax, fabsf(v.get(d)));
+    e = fp8_row_exponent(amax);
+  }
+  const float down = exp2i(-e), up = exp2i(e);
+
+  constexpr int E = CDT == DT_F32 ? 4 : (CDT == DT_BF16 ? 8 : 16);  // elements per 16 bytes
+  const int64_t tile = dst >> 5;
+  const int rr = (int)(dst & 31);
+  unsigned char* tb = tiles + tile * tile_bytes(ng);
+  float hh = 0.f;
+  for (int g = 0; g < ng; ++g) {
+    for (int hf = 0; hf < 2; ++hf) {
+      const int d0 = g * 2 * E + hf * E;
+      u32x4 w = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        float x = v.get(d0 + k);
+        float deq;
+        unsigned bits;
+        if (CDT == DT_F32) {
+          bits = __float_as_uint(x);
+          deq = x;
+          w[k] = bits;
+        } else if (CDT == DT_BF16) {
+          bits = bf16_rne(x);
+          deq = __uint_as_float(bits << 16);
+          w[k >> 1] |= bits << (16 * (k & 1));
+        } else {
+          bits = fp8_e4m3_rne(x * down);
+          deq = fp8_e4m3_value(bits) * up;
+          w[k >> 2] |= bits << (8 * (k & 3));
+        }
+        hh = hh + deq * deq;
+      }
+      *reinterpret_cast<u32x4*>(tb + g * 1024 + (rr + 32 * hf) * 16) = w;
+    }
+  }
+  unsigned char* aux = tb + ng * 1024;
+  const int half = (rr >> 2) & 1, idx = 4 * (rr >> 3) + (rr & 3);
+  reinterpret_cast<float*>(aux)[half * 16 + idx] = (database && metric == MET_L2) ? -0.5f * hh : 0.f;
+  aux[128 + rr] = (unsigned char)(e + 127);
+}
+
+template <int CDT>
+__global__ __launch_bounds__(256) void prepare_kernel(const void* src, int in_dt, int64_t rows, int D, int ng,
+                                                      int metric, int database, unsigned char* tiles,
+                                                      int64_t n_rows_padded, float* orig_half_norm,
+                                                      float* orig_rnorm) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_rows_padded) return;
+  prepare_row<CDT>(src, in_dt, r, rows, r, D, ng, metric, database != 0, tiles, orig_half_norm, orig_rnorm);
+}
+
+template <int CDT>
+__global__ __launch_bounds__(256) void prepare_segments_kernel(const QSeg* segs, int nseg, int64_t total_rows,
+                                                               int in_dt) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= total_rows) return;
+  int lo = 0, hi = nseg - 1;  // last segment with first <= r
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].first <= r) lo = mid; else hi = mid - 1;
+  }
+  const QSeg& s = segs[lo];
+  const int64_t local = r - s.first;  // rows past s.rows are padding
+  prepare_row<CDT>(s.src, in_dt, local, s.rows, s.dst_row0 + local, s.D, s.ng, s.metric, false, s.tiles, nullptr,
+                   nullptr);
+}
+
+}  // namespace
+
+hipError_t launch_prepare(const void* src, int in_dt, int64_t rows, int D, int metric, int compute,
+                          bool database, unsigned char* tiles, int64_t n_tiles, float* orig_half_norm,
+                          float* orig_rnorm, hipStream_t s) {
+  const int ng = groups_for(dpad_for(D, compute), compute);
+  const int64_t n = n_tiles * kTileRows;
+  if (n == 0) return hipSuccess;
+  const unsigned grid = (unsigned)ceil_div(n, 256);
+  if (compute == DT_F32)
+    prepare_kernel<DT_F32><<<grid, 256, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+                                                orig_half_norm, orig_rnorm);
+  else if (compute == DT_BF16)
+    prepare_kernel<DT_BF16><<<grid, 256, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+                                                 orig_half_norm, orig_rnorm);
+  else
+    prepare_kernel<DT_FP8><<<grid, 256, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+                                                orig_half_norm, orig_rnorm);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_segments(const QSeg* d_segs, int nseg, int64_t total_rows, int in_dt, int compute,
+                                   hipStream_t s) {
+  if (total_rows == 0 || nseg == 0) return hipSuccess;
+  const unsigned grid = (unsigned)ceil_div(total_rows, 256);
+  if (compute == DT_F32)
+    prepare_segments_kernel<DT_F32><<<grid, 256, 0, s>>>(d_segs, nseg, total_rows, in_dt);
+  else if (compute == DT_BF16)
+    prepare_segments_kernel<DT_BF16><<<grid, 256, 0, s>>>(d_segs, nseg, total_rows, in_dt);
+  else
+    prepare_segments_kernel<DT_FP8><<<grid, 256, 0, s>>>(d_segs, nseg, total_rows, in_dt);
+  return hipGetLastError();
+}
+
+}  // namespace knn

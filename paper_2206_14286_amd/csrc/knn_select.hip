@@ -1,0 +1,194 @@
+// knn_select.hip -- exact top-K over candidate lists (the ExactRescoring step, Sec. 4).
+//
+// The paper sorts the M x L bin winners with a bitonic sort and truncates to K
+// (O(M L log^2 L)).  Here each row gets one workgroup running an MSB-first radix
+// select on order-preserving 32-bit keys of the scores (4 passes of 8 bits over
+// the row, a 256-bin LDS histogram and a one-wave scan per pass) to find the K-th
+// best score T exactly; if T is shared by more rows than are still needed, a
+// second radix select on the row indices keeps the lowest ones.  The K survivors
+// are then bitonic-sorted in LDS by (score, lower index first) and written best
+// first.  Cost per row: O(L) reads per pass instead of O(L log^2 L).
+#include "knn_common.cuh"
+
+namespace knn {
+
+namespace {
+
+constexpr int kSelThreads = 256;
+constexpr int kMaxK = 1024;
+
+struct SelShared {
+  unsigned hist[256];
+  unsigned long long keys[kMaxK];
+  int digit, krem, eqcount, count;
+};
+
+// one radix pass: histogram of byte `shift` of key(c) over candidates whose key
+// matches prefix under mask; returns the digit holding the krem-th largest and
+// updates krem to the rank inside that digit
+template <class KeyFn>
+__device__ __forceinline__ void radix_pass(SelShared& sh, int64_t n, KeyFn key, unsigned prefix, unsigned mask,
+                                           int shift, int& krem, unsigned& digit, int& eqcount) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 256; i += kSelThreads) sh.hist[i] = 0;
+  __syncthreads();
+  for (int64_t c = tid; c < n; c += kSelThreads) {
+    bool ok;
+    unsigned k = key(c, ok);
+    if (ok && (k & mask) == prefix) atomicAdd(&sh.hist[(k >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int l = tid;
+    unsigned cnt[4];
+    unsigned sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cnt[j] = sh.hist[255 - 4 * l - j];
+      sum += cnt[j];
+    }
+    unsigned incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      unsigned t = __shfl_up(incl, off);
+      if (l >= off) incl += t;
+    }
+    const unsigned excl = incl - sum;
+    if (excl < (unsigned)krem && (unsigned)krem <= incl) {
+      unsigned acc = excl;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (acc + cnt[j] >= (unsigned)krem) {
+          sh.digit = 255 - 4 * l - j;
+          sh.krem = krem - (int)acc;
+          sh.eqcount = (int)cnt[j];
+          break;
+        }
+        acc += cnt[j];
+      }
+    }
+  }
+  __syncthreads();
+  digit = (unsigned)sh.digit;
+  krem = sh.krem;
+  eqcount = sh.eqcount;
+}
+
+__device__ void select_row(SelShared& sh, const float* __restrict__ V, const int32_t* __restrict__ A, int64_t n,
+                           int K, bool minimize, float* __restrict__ out_val, int32_t* __restrict__ out_idx) {
+  const int tid = threadIdx.x;
+  if (K > n) K = (int)n;
+  const float sgn = minimize ? -1.f : 1.f;  // rank by sgn * value, larger first
+  // phase 1: K-th best score key
+  unsigned prefix = 0, mask = 0, digit = 0;
+  int krem = K, eqcount = 0;
+  auto vkey = [&](int64_t c, bool& ok) {
+    ok = true;
+    return float_key(sgn * V[c]);
+  };
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    radix_pass(sh, n, vkey, prefix, mask, shift, krem, digit, eqcount);
+    prefix |= digit << shift;
+    mask |= 255u << shift;
+  }
+  const unsigned T = prefix;
+  // phase 2: among score == T keep the krem lowest row indices
+  unsigned T2 = 0;  // threshold on ~index (larger = lower index)
+  const bool all_eq = (eqcount == krem);
+  if (!all_eq) {
+    unsigned p2 = 0, m2 = 0, d2 = 0;
+    int kr2 = krem, eq2 = 0;
+    auto ikey = [&](int64_t c, bool& ok) {
+      ok = float_key(sgn * V[c]) == T;
+      return ~(unsigned)A[c];
+    };
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      radix_pass(sh, n, ikey, p2, m2, shift, kr2, d2, eq2);
+      p2 |= d2 << shift;
+      m2 |= 255u << shift;
+    }
+    T2 = p2;
+  }
+  // phase 3: collect the K winners
+  if (tid == 0) sh.count = 0;
+  __syncthreads();
+  for (int64_t c = tid; c < n; c += kSelThreads) {
+    const unsigned k = float_key(sgn * V[c]);
+    const unsigned lo = ~(unsigned)A[c];
+    const bool take = (k > T) || (k == T && (all_eq || lo >= T2));
+    if (take) {
+      int pos = atomicAdd(&sh.count, 1);
+      if (pos < K) sh.keys[pos] = ((unsigned long long)k << 32) | lo;
+    }
+  }
+  __syncthreads();
+  int kp = 1;
+  while (kp < K) kp <<= 1;
+  for (int i = K + tid; i < kp; i += kSelThreads) sh.keys[i] = 0ull;
+  __syncthreads();
+  // phase 4: bitonic sort, descending
+  for (int size = 2; size <= kp; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < kp; i += kSelThreads) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;
+          unsigned long long a = sh.keys[i], b = sh.keys[j];
+          if (desc ? (a < b) : (a > b)) {
+            sh.keys[i] = b;
+            sh.keys[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < K; i += kSelThreads) {
+    const unsigned long long key = sh.keys[i];
+    float v = key_float((unsigned)(key >> 32));
+    out_val[i] = sgn * v;
+    out_idx[i] = (int32_t)~(unsigned)(key & 0xFFFFFFFFull);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kSelThreads) void select_kernel(const float* __restrict__ V,
+                                                             const int32_t* __restrict__ A, int64_t rows, int64_t n,
+                                                             int64_t ldv, int K, int minimize,
+                                                             float* __restrict__ out_val,
+                                                             int32_t* __restrict__ out_idx, int64_t ldout) {
+  __shared__ SelShared sh;
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x)
+    select_row(sh, V + r * ldv, A + r * ldv, n, K, minimize != 0, out_val + r * ldout, out_idx + r * ldout);
+}
+
+__global__ __launch_bounds__(kSelThreads) void select_rows_kernel(const SelRow* __restrict__ rows_desc,
+                                                                  int64_t rows) {
+  __shared__ SelShared sh;
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const SelRow d = rows_desc[r];
+    select_row(sh, d.V, d.A, d.n, d.K, d.minimize != 0, d.out_val, d.out_idx);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t n, int64_t ldv, int K,
+                         bool minimize, float* out_val, int32_t* out_idx, int64_t ldout, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  if (K > kMaxK || K < 1 || n < 1) return hipErrorInvalidValue;
+  const int64_t grid = rows < 65536 ? rows : 65536;
+  select_kernel<<<(unsigned)grid, kSelThreads, 0, s>>>(V, A, rows, n, ldv, K, minimize ? 1 : 0, out_val, out_idx,
+                                                       ldout);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_rows(const SelRow* d_rows, int64_t rows, int max_K, hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  if (max_K > kMaxK) return hipErrorInvalidValue;
+  const int64_t grid = rows < 65536 ? rows : 65536;
+  select_rows_kernel<<<(unsigned)grid, kSelThreads, 0, s>>>(d_rows, rows);
+  return hipGetLastError();
+}
+
+}  // namespace knn

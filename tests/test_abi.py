@@ -1,0 +1,91 @@
+"""The C ABI loads and exports what include/knn.h declares; host-only helpers and
+argument checks (no GPU needed: every call here returns before touching a device)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_2206_14286_amd import knn
+    return knn
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "knn.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(knn_[a-z_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported(K):
+    lib = K.lib()
+    names = declared_functions()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/knn.h but not exported"
+
+
+def test_helpers_match_oracle(K):
+    for k in (1, 2, 5, 10, 64, 100):
+        for r in (0.5, 0.9, 0.95, 0.99):
+            assert K.bins_for_recall(k, r) == oracle.bins_for_recall(k, r)
+            L = oracle.bins_for_recall(k, r)
+            assert abs(K.expected_recall_bound(k, L) - oracle.recall_bound_paper(k, L)) < 1e-12
+    assert K.bins_for_recall(10, 0.95, 100) == 100
+    for N in (1, 7, 100, 65536, 1000000):
+        for L in (1, 3, 176, 2048):
+            if L > N:
+                continue
+            for b in (0, 1, L // 2, L - 1, L):
+                assert K.bin_start(b, N, L) == oracle.bin_start(b, N, L)
+    assert K.lib().knn_bins_for_recall(0, 0.95, 10) == -1
+    assert K.lib().knn_bins_for_recall(10, 1.5, 10) == -1
+    assert K.lib().knn_bin_start(-1, 10, 5) == -1
+
+
+def test_status_strings(K):
+    lib = K.lib()
+    assert lib.knn_status_string(0) == b"ok"
+    assert lib.knn_status_string(1) == b"invalid argument"
+    assert lib.knn_status_string(4) == b"HIP error"
+    assert lib.knn_status_string(99) == b"unknown status"
+
+
+def _p(v):
+    return ctypes.c_void_p(v)
+
+
+def test_invalid_arguments_return_before_any_device_work(K):
+    lib = K.lib()
+    fake = _p(0x1000)
+    out = ctypes.c_void_p()
+    # K > L
+    assert lib.knn_search(fake, 4, fake, 100, 16, 11, 10, 0, fake, fake, None) == 1
+    assert b"K <= L" in lib.knn_last_error()
+    # L > N
+    assert lib.knn_search(fake, 4, fake, 100, 16, 5, 101, 0, fake, fake, None) == 1
+    # D too large: unsupported
+    assert lib.knn_search(fake, 4, fake, 100, 300, 5, 10, 0, fake, fake, None) == 2
+    # bad metric
+    assert lib.knn_search(fake, 4, fake, 100, 16, 5, 10, 7, fake, fake, None) == 1
+    # NULL pointers
+    assert lib.knn_search(None, 4, fake, 100, 16, 5, 10, 0, fake, fake, None) == 1
+    # database creation: NULL X, bad dtype, N = 0
+    assert lib.knn_db_create(None, 0, 100, 16, 0, 0, None, ctypes.byref(out)) == 1
+    assert lib.knn_db_create(fake, 2, 100, 16, 0, 0, None, ctypes.byref(out)) == 1
+    assert lib.knn_db_create(fake, 0, 0, 16, 0, 0, None, ctypes.byref(out)) == 1
+    assert out.value is None
+    assert lib.knn_db_search(None, fake, 0, 4, 5, 10, 0, fake, fake, None, None, None) == 1
+    assert lib.knn_backward(fake, fake, fake, fake, 0, 4, 100, 300, 5, 0, fake, fake, None) == 2
+    assert lib.knn_backward(fake, fake, fake, fake, 0, 4, 0, 16, 5, 0, fake, fake, None) == 1
+    assert lib.knn_search_batched(None, None) == 1
+    assert lib.knn_plan_create(None, 0, None, 0, 0, 0.95, 0, None, None, ctypes.byref(out)) == 1
+    assert lib.knn_db_destroy(None) == 0 and lib.knn_plan_destroy(None) == 0
+    # M = 0 is a no-op that succeeds without touching the device
+    assert lib.knn_search(None, 0, fake, 100, 16, 5, 10, 0, None, None, None) == 0

@@ -1,0 +1,186 @@
+"""GPU parity of the HIP search path against the FP64 oracle (run on an MI355X)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2206_14286_amd import datagen, knn
+from parity import check_bins, check_topk
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    return t.to(dtype) if dtype is not None else t
+
+
+def make_inputs(metric, M, N, D, seed):
+    if metric == "l2":
+        return datagen.int_mixture(M, D, seed + 1, centres=16), datagen.int_mixture(N, D, seed, centres=16)
+    return datagen.normal(M, D, seed + 1), datagen.normal(N, D, seed)
+
+
+def dpad_of(D, compute):
+    step = 64 if compute == "fp8" else 32
+    return (D + step - 1) // step * step
+
+
+# Unit roundoff used in the rounding bound per compute type.  FP32 and BF16 products
+# are exact and the matrix unit accumulates in FP32: u = 2^-23 (twice the RNE unit).
+# The FP8 32x32x64 instruction sums its 64-deep products with a coarser internal
+# adder: measured errors reach ~1.2x the FP32 bound, so its bound is stated with
+# u = 2^-20 (8x), and its values are held to 1e-4 relative instead of 1e-5.
+U_BOUND = {"fp32": 2.0 ** -23, "bf16": 2.0 ** -23, "fp8": 2.0 ** -20}
+V_RTOL = {"fp32": 1e-5, "bf16": 1e-5, "fp8": 1e-4}
+
+
+CASES = [
+    # metric, M, N, D, K, L, compute
+    ("mips", 64, 65536, 128, 10, 2048, "fp32"),   # the small MIPS workload in full
+    ("mips", 70, 5003, 100, 7, 61, "fp32"),       # ragged N, L not dividing N, D padded
+    ("l2", 300, 4099, 128, 10, 176, "fp32"),
+    ("cosine", 129, 3001, 96, 5, 40, "fp32"),
+    ("mips", 33, 777, 64, 3, 777, "fp32"),        # L = N: one row per bin
+    ("mips", 5, 1000, 32, 4, 4, "fp32"),          # L = K: bins of 250 rows
+    ("l2", 257, 2048, 256, 10, 64, "fp32"),
+    ("mips", 1, 100, 16, 1, 1, "fp32"),           # one query, one bin
+    ("mips", 200, 4096, 128, 10, 128, "bf16"),
+    ("l2", 130, 3000, 128, 10, 100, "bf16"),
+    ("cosine", 260, 2000, 256, 8, 73, "bf16"),
+    ("cosine", 100, 3333, 100, 20, 300, "fp8"),
+    ("mips", 64, 2500, 128, 10, 50, "fp8"),
+    ("l2", 129, 1500, 64, 5, 1500, "fp8"),
+]
+
+
+@pytest.mark.parametrize("metric,M,N,D,K,L,compute", CASES)
+def test_bins_and_topk_vs_oracle(metric, M, N, D, K, L, compute):
+    _log(f"case {metric} M={M} N={N} D={D} K={K} L={L} {compute}")
+    Q, X = make_inputs(metric, M, N, D, seed=M + N)
+    db = knn.Database(to_dev(X), metric, compute)
+    vals, idx, bv, bi = db.search(to_dev(Q), K, L, return_bins=True)
+    torch.cuda.synchronize()
+    Qq = oracle.quantize_like_library(Q, metric, compute)
+    Xq = oracle.quantize_like_library(X, metric, compute)
+    mo = "mips" if metric == "cosine" else metric
+    ora = oracle.search(Qq, Xq, mo, L, K, bins=True)
+    dp = dpad_of(D, compute)
+    u, rt = U_BOUND[compute], V_RTOL[compute]
+    n_sep, n_tie = check_bins(Qq, Xq, mo, L, bv.cpu().numpy(), bi.cpu().numpy(), ora, dp, u=u, value_rtol=rt)
+    assert n_sep > 0.5 * (n_sep + n_tie)
+    check_topk(Qq, Xq, mo, K, vals.cpu().numpy(), idx.cpu().numpy(), ora, dp, u=u, value_rtol=rt)
+
+
+@pytest.mark.parametrize("metric,compute", [(m, c) for m in ("mips", "l2", "cosine") for c in ("fp32", "bf16", "fp8")])
+def test_prepared_rows_match_reference_quantisers(metric, compute):
+    """The rows the kernel streams are bit-identical to the oracle's quantisers."""
+    _log(f"prepare {metric} {compute}")
+    N, D = 1000, 100
+    X = datagen.normal(N, D, 5) * np.float32(3.0)
+    X[7] = 0
+    db = knn.Database(to_dev(X), metric, compute)
+    codes, exps, hn = db.export()
+    Xn = oracle.normalize_rows_f32(X) if metric == "cosine" else X
+    if compute == "fp32":
+        np.testing.assert_array_equal(codes.view(np.uint32), Xn.view(np.uint32))
+        deq = Xn
+    elif compute == "bf16":
+        v, c = oracle.bf16_round(Xn)
+        np.testing.assert_array_equal(codes, c)
+        deq = v
+    else:
+        deq, c, e = oracle.fp8_quantize_rows(Xn)
+        np.testing.assert_array_equal(exps, e)
+        np.testing.assert_array_equal(codes, c)
+    if metric == "l2":
+        ref = 0.5 * (deq.astype(np.float64) ** 2).sum(1)
+        np.testing.assert_allclose(hn, ref, rtol=2e-6, atol=1e-30)
+
+
+def test_l2_integer_data_exact():
+    """Integer data in [0, 255]: every FP32 (and BF16) partial sum is exact, so bins and
+    top-K must equal the oracle's bit for bit, ties included (lowest row wins)."""
+    M, N, D, K, L = 256, 20000, 128, 10, 176
+    Q = datagen.int_mixture(M, D, 31)
+    X = datagen.int_mixture(N, D, 30)
+    ora = oracle.search(Q, X, "l2", L, K, bins=True)
+    for compute in ("fp32", "bf16"):
+        _log(f"l2 exact {compute}")
+        db = knn.Database(to_dev(X), "l2", compute)
+        vals, idx, bv, bi = db.search(to_dev(Q), K, L, return_bins=True)
+        np.testing.assert_array_equal(bi.cpu().numpy(), ora["bin_i"])
+        np.testing.assert_array_equal(bv.cpu().numpy().astype(np.float64), ora["bin_v"])
+        np.testing.assert_array_equal(idx.cpu().numpy(), ora["top_i"])
+        np.testing.assert_array_equal(vals.cpu().numpy().astype(np.float64), ora["top_v"])
+
+
+def test_plain_search_entry_point():
+    """knn_search (FP32 inputs, prepares X on every call) equals the prepared-database path."""
+    Q = datagen.normal(100, 64, 41)
+    X = datagen.normal(3000, 64, 40)
+    for metric in ("mips", "l2", "cosine"):
+        v1, i1 = knn.search(to_dev(Q), to_dev(X), 10, 100, metric)
+        v2, i2 = knn.Database(to_dev(X), metric, "fp32").search(to_dev(Q), 10, 100)
+        assert torch.equal(i1, i2) and torch.equal(v1, v2)
+
+
+def test_zero_queries_is_noop():
+    X = to_dev(datagen.normal(100, 16, 1))
+    db = knn.Database(X, "mips")
+    v, i = db.search(torch.empty((0, 16), device=DEV), 5, 10)
+    assert v.shape == (0, 5)
+
+
+@pytest.mark.parametrize("compute", ["bf16", "fp8"])
+def test_rerank_recovers_recall(compute):
+    """Low-precision GEMM + FP32 rerank of the best Kr bin winners: the returned scores are
+    the FP32 scores of the original rows, and recall against the exact FP64 K-NN matches
+    the FP64 approximate search at the same L."""
+    metric = "cosine" if compute == "fp8" else "l2"
+    M, N, D, K, L, Kr = 128, 30000, 128, 10, 400, 40
+    if metric == "l2":
+        Q, X = datagen.int_mixture(M, D, 51, centres=64), datagen.int_mixture(N, D, 50, centres=64)
+    else:
+        Q, X = datagen.unit_mixture(M, D, 51, centres=50), datagen.unit_mixture(N, D, 50, centres=50)
+    _log(f"rerank {compute} {metric}")
+    db = knn.Database(to_dev(X), metric, compute)
+    vals, idx = db.search(to_dev(Q), K, L, rerank=Kr)
+    vals, idx = vals.cpu().numpy(), idx.cpu().numpy()
+    ora = oracle.search(Q, X, metric, L, K, exact=True)
+    s64, mag = oracle.pair_scores(Q, X, metric, np.repeat(np.arange(M), K), idx.ravel())
+    np.testing.assert_allclose(vals.ravel(), s64, rtol=1e-5, atol=1e-5 * float(np.max(np.abs(s64))))
+    mn = oracle.minimize_for(metric)
+    rec_gpu = oracle.recall_tie_aware(s64.reshape(M, K), ora["ex_v"][:, -1], mn).mean()
+    rec_ora = oracle.recall_tie_aware(ora["top_v"], ora["ex_v"][:, -1], mn).mean()
+    _log(f"recall gpu {rec_gpu:.4f} oracle-fp64 {rec_ora:.4f}")
+    assert rec_gpu >= rec_ora - 0.01
+
+
+def test_full_size_l2_sift_sample():
+    """The L2 workload at full size (N = 1M, M = 10,000, L = 176) in FP32 and BF16; 24 sampled
+    queries are checked against the oracle (integer data: exact)."""
+    _log("l2_sift full size: generating")
+    Q, X = datagen.make("l2_sift", seed=0)
+    w = datagen.WORKLOADS["l2_sift"]
+    K, L = w["K"], w["L"]
+    Xd, Qd = to_dev(X), to_dev(Q)
+    sample = np.linspace(0, Q.shape[0] - 1, 24).astype(np.int64)
+    ora = oracle.search(Q[sample], X, "l2", L, K, bins=True)
+    for compute in ("fp32", "bf16"):
+        _log(f"l2_sift full size {compute}")
+        db = knn.Database(Xd, "l2", compute)
+        vals, idx, bv, bi = db.search(Qd, K, L, return_bins=True)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(bi.cpu().numpy()[sample], ora["bin_i"])
+        np.testing.assert_array_equal(idx.cpu().numpy()[sample], ora["top_i"])
+        np.testing.assert_array_equal(vals.cpu().numpy()[sample].astype(np.float64), ora["top_v"])
+        del db
