@@ -81,7 +81,7 @@ def run_variant(knn, Xd, Qd, w, compute, rerank, steps, warmup, sample_idx):
     # the distance + bin-reduce kernel alone, on prepared queries
     qbuf = db.prepare_queries(Qd)
     bins = (torch.empty((M, L), dtype=torch.float32, device="cuda"), torch.empty((M, L), dtype=torch.int32, device="cuda"))
-    ksec = time_kernel_events(lambda: db.partial_reduce(qbuf, M, L, out=bins), max(steps, 5))
+    ksec = time_kernel_events(lambda: db.partial_reduce(qbuf, M, L, out=bins, resolve=False), max(steps, 5))
     flops = 2.0 * M * N * dpad(D, compute)
     res = {
         "compute": compute,
@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--recall-sample", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a known-size kernel for "
+                         "scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding); "
@@ -134,6 +137,14 @@ def main():
     rng = np.random.default_rng(1)
     sample = np.sort(rng.choice(M, args.recall_sample, replace=False))
     sample_t = torch.from_numpy(sample).cuda()
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     results = {}
     for comp in [args.compute] + [c for c in args.variants.split(",") if c and c != args.compute]:

@@ -141,12 +141,21 @@ knn_status knn_db_search(const knn_db* db, const void* Q, int32_t q_dtype, int64
  *   of at least knn_query_buffer_bytes(db, M) bytes, owned by the caller.
  * knn_partial_reduce: PartialReduce alone (Sec. 4, Algorithm 1): the M x L bin winners
  *   (bins_val FP32, bins_idx int32, device, row-major), compute-type scores in the
- *   metric's own sign; no top-K (the `aggregate_to_topk = False` form of the paper's op). */
+ *   metric's own sign; no top-K (the `aggregate_to_topk = False` form of the paper's op).
+ *   bins_idx is in compact form: an entry >= 0 is the winning row; an entry e <= -2
+ *   says the winner is one of the 4 rows starting at row 4*(-2-e) (the kernel tracks
+ *   the best of each 4-row group of its accumulators); -1 means no finite score.
+ * knn_resolve_rows: replaces every compact entry of idx (M x ncols, leading dimension
+ *   ld, row i belonging to query i of qbuf) by the exact row: the 4 rows are rescored
+ *   from the prepared rows in FP32 and the best (lowest row on ties) is kept.
+ *   knn_db_search does this itself; its outputs always hold exact rows. */
 size_t knn_query_buffer_bytes(const knn_db* db, int64_t M);
 knn_status knn_query_prepare(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, void* qbuf,
                              size_t qbuf_bytes, void* stream);
 knn_status knn_partial_reduce(const knn_db* db, const void* qbuf, int64_t M, int64_t L, float* bins_val,
                               int32_t* bins_idx, void* stream);
+knn_status knn_resolve_rows(const knn_db* db, const void* qbuf, int64_t M, int64_t ncols, int32_t* idx, int64_t ld,
+                            void* stream);
 
 /* ------------------------------------------------------------------ batched search */
 

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libknn_mi355x.so")
-SOURCES = ["knn_prepare.hip", "knn_fused.hip", "knn_select.hip", "knn_rerank_backward.hip", "knn_api.cpp"]
+SOURCES = ["knn_prepare.hip", "knn_fused.hip", "knn_select.hip", "knn_resolve.hip", "knn_rerank_backward.hip",
+           "knn_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -26,9 +27,14 @@ FLAGS = [
 ]
 
 
+# per-file extras: the distance kernel assumes finite scores (as the C ABI states), which
+# lets max() of matrix-unit results compile to plain v_max/v_max3 without NaN quieting
+EXTRA = {"knn_fused.hip": ["-fno-honor-nans"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -70,7 +70,7 @@ int pick_ncb(int dt, int ng, int64_t M) {
 }
 
 // bins per work item: enough items to fill the chip, at least ~256 rows per item
-int64_t pick_bins_per_chunk(int64_t N, int64_t L, int64_t n_qb, int64_t target_items = 2048) {
+int64_t pick_bins_per_chunk(int64_t N, int64_t L, int64_t n_qb, int64_t target_items = 8192) {
   const double bin_rows = double(N) / double(L);
   int64_t want_chunks = std::max<int64_t>(1, ceil_div(target_items, std::max<int64_t>(1, n_qb)));
   int64_t bpc = std::max<int64_t>(1, L / want_chunks);
@@ -117,7 +117,7 @@ struct knn_plan {
   std::vector<GroupPlan> groups;
   int32_t q_dtype = KNN_F32, compute = KNN_BF16;
   int64_t total_q_rows = 0, n_items = 0, n_sel_rows = 0;
-  int n_blocks = 0, max_ng = 0, n_segs = 0, max_K = 1;
+  int n_blocks = 0, max_ng = 0, n_segs = 0, max_K = 1, lds_bytes = 0;
   QSeg* d_segs = nullptr;
   GroupDesc* d_groups = nullptr;
   WorkItem* d_items = nullptr;
@@ -292,15 +292,20 @@ static knn_status search_core(const knn_db* db, const void* Q, int32_t q_dtype, 
   p.binA = binA;
   p.ldo = L;
   HIP_TRY(launch_fused(dt, ng, ncb, p, s), "distance + bin-reduce kernel");
+  const unsigned char* qt = (const unsigned char*)qbuf.p;
+  if (bins_idx) HIP_TRY(launch_resolve(dt, binA, M, L, L, qt, db->tiles, ng, s), "resolve bin winners");
   const bool minimize = db->metric == KNN_L2;
   if (rerank_k <= 0) {
     HIP_TRY(launch_select(binV, binA, M, L, L, K, minimize, out_val, out_idx, K, s), "top-K select");
+    HIP_TRY(launch_resolve(dt, out_idx, M, K, K, qt, db->tiles, ng, s), "resolve top-K rows");
     return KNN_OK;
   }
   HIP_TRY(cbufv.alloc(sizeof(float) * (size_t)(M * rerank_k), s), "hipMallocAsync (candidates)");
   HIP_TRY(cbufi.alloc(sizeof(int32_t) * (size_t)(M * rerank_k), s), "hipMallocAsync (candidates)");
   HIP_TRY(launch_select(binV, binA, M, L, L, rerank_k, minimize, (float*)cbufv.p, (int32_t*)cbufi.p, rerank_k, s),
           "top-K select (rerank candidates)");
+  HIP_TRY(launch_resolve(dt, (int32_t*)cbufi.p, M, rerank_k, rerank_k, qt, db->tiles, ng, s),
+          "resolve rerank candidates");
   HIP_TRY(launch_rerank((const int32_t*)cbufi.p, M, rerank_k, Q, q_dtype, db->X, db->in_dt, db->D, db->metric,
                         db->orig_half_norm, db->orig_rnorm, K, out_val, out_idx, s),
           "FP32 rerank");
@@ -411,6 +416,18 @@ extern "C" knn_status knn_partial_reduce(const knn_db* db, const void* qbuf, int
   return KNN_OK;
 }
 
+extern "C" knn_status knn_resolve_rows(const knn_db* db, const void* qbuf, int64_t M, int64_t ncols, int32_t* idx,
+                                       int64_t ld, void* stream) {
+  g_last_error.clear();
+  if (!db) return fail(KNN_ERR_INVALID, "db is NULL");
+  if (M < 0 || ncols < 0 || ld < ncols) return fail(KNN_ERR_INVALID, "bad sizes");
+  if (M > 0 && ncols > 0 && (!qbuf || !idx)) return fail(KNN_ERR_INVALID, "NULL buffer");
+  HIP_TRY(launch_resolve(db->compute, idx, M, ncols, ld, (const unsigned char*)qbuf, db->tiles, db->ng,
+                         (hipStream_t)stream),
+          "resolve rows");
+  return KNN_OK;
+}
+
 // --------------------------------------------------------------------------- backward
 extern "C" knn_status knn_backward(const float* g, const int32_t* idx, const void* Q, const void* X,
                                    int32_t in_dtype, int64_t M, int64_t N, int32_t D, int32_t K, int32_t metric,
@@ -457,6 +474,7 @@ knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
   std::vector<SelRow> sel;
   int64_t first = 0;
   p->max_ng = 0;
+  p->lds_bytes = 0;
   for (size_t gi = 0; gi < p->groups.size(); ++gi) {
     GroupPlan& g = p->groups[gi];
     const knn_db* db = p->dbs[g.db];
@@ -465,6 +483,7 @@ knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
     g.q_tiles_n = g.n_qb * QB / kTileRows;
     g.n_chunks = ceil_div(g.L, g.bins_per_chunk);
     p->max_ng = std::max(p->max_ng, db->ng);
+    p->lds_bytes = std::max(p->lds_bytes, fused_lds_bytes(db->ng, g.ncb));
     if (hipMalloc(&g.q_tiles, (size_t)(g.q_tiles_n * tile_bytes(db->ng))) != hipSuccess ||
         hipMalloc(&g.binV, sizeof(float) * (size_t)std::max<int64_t>(1, g.M * g.L)) != hipSuccess ||
         hipMalloc(&g.binA, sizeof(int32_t) * (size_t)std::max<int64_t>(1, g.M * g.L)) != hipSuccess)
@@ -492,6 +511,10 @@ knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
         sr.minimize = db->metric == KNN_L2;
         sr.out_val = b.out_val + r * b.K;
         sr.out_idx = b.out_idx + r * b.K;
+        sr.q_tiles = g.q_tiles;
+        sr.db_tiles = db->tiles;
+        sr.q_row = row + r;
+        sr.ng = db->ng;
         sel.push_back(sr);
       }
       first += b.M;
@@ -581,9 +604,10 @@ knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
 knn_status run_plan(knn_plan* p, hipStream_t s) {
   HIP_TRY(launch_prepare_segments(p->d_segs, p->n_segs, p->total_q_rows, p->q_dtype, p->compute, s),
           "batched query preparation");
-  HIP_TRY(launch_fused_persistent(p->compute, p->d_groups, p->d_items, p->n_items, p->n_blocks, p->max_ng, s),
+  HIP_TRY(launch_fused_persistent(p->compute, p->d_groups, p->d_items, p->n_items, p->n_blocks, p->lds_bytes, s),
           "persistent distance + bin-reduce kernel");
   HIP_TRY(launch_select_rows(p->d_sel, p->n_sel_rows, p->max_K, s), "batched top-K select");
+  HIP_TRY(launch_resolve_rows(p->compute, p->d_sel, p->n_sel_rows, s), "batched resolve");
   return KNN_OK;
 }
 

@@ -37,103 +37,205 @@ constexpr int kSlowFloats = 2 * 32 * 33;  // per-wave scratch: 2 column blocks x
 
 template <int NG>
 struct TileGeom {
-  static constexpr int kChunks = NG * 64 + kAuxBytes / 16;        // 16-byte pieces of a tile
-  static constexpr int kPerWave = (kChunks + 64 * kWaves - 1) / (64 * kWaves);
-  static constexpr int kLdsBytes = kPerWave * 64 * kWaves * 16;    // buffer incl. landing pad
+  static constexpr int kMain = NG * 64;                                     // 16-byte pieces of fragments
+  static constexpr int kPerWave = (kMain + 64 * kWaves - 1) / (64 * kWaves);  // fragment loads per wave
+  static constexpr int kLoads = kPerWave + 1;                               // + one aux load per wave
+  static constexpr int kMainBytes = kPerWave * 64 * kWaves * 16;            // incl. landing pad
+  static constexpr int kLdsBytes = kMainBytes + kAuxBytes;
+  // pipeline depth: deep for the short low-precision tiles, double buffering for FP32-size tiles
+  static constexpr int kStages = NG <= 8 ? 4 : 2;
 };
 
-template <int NG, int NCB>
+template <int NG>
 constexpr int lds_bytes() {
-  return 2 * TileGeom<NG>::kLdsBytes + kWaves * kSlowFloats * 4;
+  return TileGeom<NG>::kStages * TileGeom<NG>::kLdsBytes + kWaves * kSlowFloats * 4;
 }
 
-__device__ __forceinline__ void wait_vmcnt0() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// wait until at most N vector-memory loads of this wave are outstanding
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
 
-// copy one prepared tile (NG KiB + aux) into LDS with direct global->LDS loads;
-// every wave issues the same number of loads (pieces past the end re-read the
-// last piece and land in the buffer's pad) so vmcnt counts are uniform
+// Per-lane byte offsets of the 16-byte pieces a lane moves when a tile is copied
+// into LDS; the same for every tile of an item, so they are computed once and the
+// loads use a uniform tile base plus these offsets.
 template <int NG>
-__device__ __forceinline__ void load_tile(const unsigned char* __restrict__ src, unsigned char* lds_dst) {
+struct TileLoadPlan {
+  unsigned frag_off[TileGeom<NG>::kPerWave];
+  unsigned aux_off;
+};
+
+template <int NG>
+__device__ __forceinline__ TileLoadPlan<NG> make_load_plan(int wave, int lane) {
   using G = TileGeom<NG>;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  TileLoadPlan<NG> p;
 #pragma unroll
   for (int it = 0; it < G::kPerWave; ++it) {
-    int k = it * 64 * kWaves + wave * 64 + lane;
-    int kc = k < G::kChunks ? k : G::kChunks - 1;
+    const int k = it * 64 * kWaves + wave * 64 + lane;
+    p.frag_off[it] = (unsigned)(k < G::kMain ? k : G::kMain - 1) * 16u;
+  }
+  p.aux_off = (unsigned)(NG * 1024 + (wave * 4 + (lane & 3)) * 16);
+  return p;
+}
+
+// copy one prepared tile (NG KiB of fragments + 256 B aux) into LDS with direct
+// global->LDS loads.  Every wave issues the same number of loads (kLoads): pieces
+// past the end re-read the last fragment piece and land in the buffer's pad, and
+// each wave moves a quarter of the aux block with four lanes, so per-wave vmcnt
+// counts are uniform and a tile's arrival can be awaited with one immediate.
+// `wave` must be wave-uniform (an SGPR value): the LDS destination of each load is.
+template <int NG>
+__device__ __forceinline__ void load_tile(const unsigned char* __restrict__ src, unsigned char* lds_dst,
+                                          const TileLoadPlan<NG>& p, int wave, int lane) {
+  using G = TileGeom<NG>;
+#pragma unroll
+  for (int it = 0; it < G::kPerWave; ++it) {
     unsigned char* dst = lds_dst + (it * 64 * kWaves + wave * 64) * 16;
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + (int64_t)kc * 16),
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + p.frag_off[it]),
+                                     (__attribute__((address_space(3))) void*)(dst), 16, 0, 0);
+  }
+  if (lane < 4) {
+    unsigned char* dst = lds_dst + G::kMainBytes + wave * 64;
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + p.aux_off),
                                      (__attribute__((address_space(3))) void*)(dst), 16, 0, 0);
   }
 }
 
+// one tile's A operand fragments, accumulator start values (-|x|^2/2 for L2) and
+// FP8 row scale, as read from LDS
+template <int NG>
+struct TileRegs {
+  u32x4 af[NG];
+  f32x16 init;
+  int sa;
+};
+
+template <int NG>
+__device__ __forceinline__ void read_tile(TileRegs<NG>& r, const unsigned char* tile) {
+  using G = TileGeom<NG>;
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+#pragma unroll
+  for (int g = 0; g < NG; ++g) r.af[g] = *reinterpret_cast<const u32x4*>(tile + g * 1024 + lane * 16);
+  const float* auxf = reinterpret_cast<const float*>(tile + G::kMainBytes);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) r.init[i] = auxf[h * 16 + i];
+  r.sa = tile[G::kMainBytes + 128 + (lane & 31)];
+}
+
+// acc[cb] = init + sum over the tile depth of A(tile rows) x B(query columns)
 template <int DT, int NG, int NCB>
-struct MmaTile {
-  // acc[cb] = init + sum over the tile depth of A(tile rows) x B(query columns)
-  static __device__ __forceinline__ void run(f32x16 (&acc)[NCB], const unsigned char* tile,
-                                             const u32x4 (&bq)[NCB][NG], const f32x16& init, int sa,
-                                             const int (&sb)[NCB]) {
-    const int lane = threadIdx.x & 63;
-    if constexpr (DT == DT_FP8) {
-      u32x4 af[NG];
+__device__ __forceinline__ void mma_tile(f32x16 (&acc)[NCB], const TileRegs<NG>& r, const u32x4 (&bq)[NCB][NG],
+                                         const int (&sb)[NCB]) {
+  if constexpr (DT == DT_FP8) {
 #pragma unroll
-      for (int g = 0; g < NG; ++g) af[g] = *reinterpret_cast<const u32x4*>(tile + g * 1024 + lane * 16);
+    for (int s = 0; s < NG / 2; ++s) {
+      const u32x4& a0 = r.af[2 * s];
+      const u32x4& a1 = r.af[2 * s + 1];
+      i32x8 A = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
 #pragma unroll
-      for (int s = 0; s < NG / 2; ++s) {
-        const u32x4& a0 = af[2 * s];
-        const u32x4& a1 = af[2 * s + 1];
-        i32x8 A = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+      for (int cb = 0; cb < NCB; ++cb) {
+        const u32x4& b0 = bq[cb][2 * s];
+        const u32x4& b1 = bq[cb][2 * s + 1];
+        i32x8 B = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+        acc[cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, B, s == 0 ? r.init : acc[cb], 0, 0, 0, r.sa, 0,
+                                                                   sb[cb]);
+      }
+    }
+  } else if constexpr (DT == DT_BF16) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      bf16x8 A = __builtin_bit_cast(bf16x8, r.af[g]);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        bf16x8 B = __builtin_bit_cast(bf16x8, bq[cb][g]);
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, g == 0 ? r.init : acc[cb], 0, 0, 0);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
-          const u32x4& b0 = bq[cb][2 * s];
-          const u32x4& b1 = bq[cb][2 * s + 1];
-          i32x8 B = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
-          acc[cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, B, s == 0 ? init : acc[cb], 0, 0, 0, sa, 0,
-                                                                     sb[cb]);
-        }
-      }
-    } else if constexpr (DT == DT_BF16) {
-      u32x4 af[NG];
-#pragma unroll
-      for (int g = 0; g < NG; ++g) af[g] = *reinterpret_cast<const u32x4*>(tile + g * 1024 + lane * 16);
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        bf16x8 A = __builtin_bit_cast(bf16x8, af[g]);
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          bf16x8 B = __builtin_bit_cast(bf16x8, bq[cb][g]);
-          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, g == 0 ? init : acc[cb], 0, 0, 0);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        u32x4 a = *reinterpret_cast<const u32x4*>(tile + g * 1024 + lane * 16);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) {
-            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[e]), __uint_as_float(bq[cb][g][e]),
-                                                           (g == 0 && e == 0) ? init : acc[cb], 0, 0, 0);
-          }
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(r.af[g][e]), __uint_as_float(bq[cb][g][e]),
+                                                         (g == 0 && e == 0) ? r.init : acc[cb], 0, 0, 0);
         }
       }
     }
   }
-};
-
-// merge the two lane halves' (value, row) of one query: larger value, then lower row
-__device__ __forceinline__ void merge_halves(float v, int i, float& mv, int& mi) {
-  float ov = __shfl_xor(v, 32);
-  int oi = __shfl_xor(i, 32);
-  bool take = (ov > v) || (ov == v && oi < i);
-  mv = take ? ov : v;
-  mi = take ? oi : i;
 }
 
+// A bin's running winner is a "unit": either one exact row or a group of 4
+// consecutive rows (one lane's accumulators 4k..4k+3) whose exact row is resolved
+// later from the prepared rows.  Units are keyed u = 2*start + is_group (unsigned,
+// 0xFFFFFFFF = none); units of one bin never overlap, so ordering by u orders by row.
+constexpr unsigned kNoUnit = 0xFFFFFFFFu;
+
+// merge the two lane halves' (value, unit) of one query: larger value, then lower unit
+__device__ __forceinline__ void merge_halves(float v, unsigned u, float& mv, unsigned& mu) {
+  const float ov = __shfl_xor(v, 32);
+  const unsigned ou = __shfl_xor(u, 32);
+  const bool take = (ov > v) || (ov == v && ou < u);
+  mv = take ? ov : v;
+  mu = take ? ou : u;
+}
+
+// bins output: value in the metric's sign; row >= 0, or -2 - start/4 for a 4-row group
+// starting at row `start`, or -1 when the bin saw no finite score
 __device__ __forceinline__ void write_bin(float* __restrict__ outV, int32_t* __restrict__ outA, int64_t ldo,
-                                          int64_t q, int64_t bin, float v, int idx, float sign) {
+                                          int64_t q, int64_t bin, float v, unsigned u, float sign) {
   outV[q * ldo + bin] = sign * v;
-  outA[q * ldo + bin] = idx >= kSentinel ? -1 : idx;
+  int32_t code = -1;
+  if (u != kNoUnit) code = (u & 1u) ? -2 - (int32_t)(u >> 3) : (int32_t)(u >> 1);
+  outA[q * ldo + bin] = code;
+}
+
+// scheduling hint for one pipelined step: the LDS reads of the next tile's
+// fragments go first, then each matrix instruction of the next tile alternates
+// with a few VALU instructions of the current tile's bin update, so the reads'
+// latency and the bin update both hide behind the matrix unit inside one wave
+template <int N, int V>
+__device__ __forceinline__ void interleave_hint() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x002, V, 0);  // VALU
+    interleave_hint<N - 1, V>();
+  }
+}
+
+template <int DT, int NG, int NCB>
+struct StepShape {
+  static constexpr int kMfma = DT == DT_FP8 ? (NG / 2) * NCB : (DT == DT_BF16 ? NG * NCB : 4 * NG * NCB);
+  static constexpr int kValu = 24 * NCB;  // fast bin update: ~5 per 4 scores + unit arithmetic
+  static constexpr int kValuPer = (kValu + kMfma - 1) / kMfma;
+};
+
+// The fast bin update of one tile (every row of the tile in the current bin): per
+// lane the max of each group of 4 accumulators (rows t0 + 8k + 4h + 0..3), compared
+// with the running best in row order; returns the updated state in nbv/nbu.
+template <int NCB>
+__device__ __forceinline__ void fast_update(const f32x16 (&acc)[NCB], const float (&bv)[NCB],
+                                            const unsigned (&bu)[NCB], float (&nbv)[NCB], unsigned (&nbu)[NCB],
+                                            unsigned ubase) {
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    nbv[cb] = bv[cb];
+    nbu[cb] = bu[cb];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const float gk =
+          fmaxf(fmaxf(fmaxf(acc[cb][4 * k], acc[cb][4 * k + 1]), acc[cb][4 * k + 2]), acc[cb][4 * k + 3]);
+      const bool c = gk > nbv[cb];
+      nbv[cb] = c ? gk : nbv[cb];
+      nbu[cb] = c ? ubase + 16u * k : nbu[cb];
+    }
+  }
 }
 
 template <int DT, int NG, int NCB>
@@ -142,16 +244,20 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
                                          int64_t q0, int64_t b0, int64_t b1, float sign, float* __restrict__ outV,
                                          int32_t* __restrict__ outA, int64_t ldo, unsigned char* lds) {
   using G = TileGeom<NG>;
+  using SS = StepShape<DT, NG, NCB>;
+  constexpr int S = G::kStages;
+  static_assert((S & (S - 1)) == 0 && S >= 2, "stages: a power of two >= 2");
   constexpr int64_t TB = (int64_t)NG * 1024 + kAuxBytes;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int h = lane >> 5, ql = lane & 31;
-  unsigned char* buf0 = lds;
-  unsigned char* buf1 = lds + G::kLdsBytes;
-  float* scratch = reinterpret_cast<float*>(lds + 2 * G::kLdsBytes) + wave * kSlowFloats;
+  float* scratch = reinterpret_cast<float*>(lds + S * G::kLdsBytes) + wave * kSlowFloats;
+  const TileLoadPlan<NG> plan = make_load_plan<NG>(wave, lane);
 
-  const int64_t r0 = bin_start(b0, N, L), r1 = bin_start(b1, N, L);
-  const int64_t t_first = r0 >> 5, t_last = (r1 - 1) >> 5;
-  load_tile<NG>(db_tiles + t_first * TB, buf0);
+  // rows and tiles fit in 32 bits (N < 2^31)
+  const int r0 = (int)bin_start(b0, N, L), r1 = (int)bin_start(b1, N, L);
+  const int t_first = r0 >> 5, t_last = (r1 - 1) >> 5;
+  auto buf = [&](int t) { return lds + ((t - t_first) & (S - 1)) * G::kLdsBytes; };
 
   // query fragments of this wave (tiles of 32 queries; the buffer is padded)
   const int64_t wq0 = q0 + (int64_t)wave * 32 * NCB;
@@ -166,144 +272,159 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   }
   const bool active = wq0 < M;
 
-  // running bin state per column block and lane half: best value, the tile (first
-  // row) it came from and the row offset inside the tile, so the per-score index
-  // update only moves an inline constant
+  // running bin state per column block and lane half: best value bv and its unit bu
   float bv[NCB];
-  int bt[NCB], bo[NCB];
+  unsigned bu[NCB];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) {
     bv[cb] = -INFINITY;
-    bt[cb] = kSentinel;
-    bo[cb] = 0;
+    bu[cb] = kNoUnit;
   }
-  auto abs_index = [&](int cb) { return bt[cb] == kSentinel ? kSentinel : bt[cb] + bo[cb] + 4 * h; };
-  int64_t cur_bin = b0;
-  int64_t next_start = bin_start(b0 + 1, N, L);
+  int cur_bin = (int)b0;
+  int next_start = (int)bin_start(b0 + 1, N, L);
 
-  for (int64_t t = t_first; t <= t_last; ++t) {
-    unsigned char* cur = ((t - t_first) & 1) ? buf1 : buf0;
-    unsigned char* nxt = ((t - t_first) & 1) ? buf0 : buf1;
-    wait_vmcnt0();
+  // Software pipeline over the chunk's tiles.  Step t: the tile loads run S tiles
+  // ahead (direct global->LDS); the fragments of tile t+1 are read from LDS and
+  // its matrix instructions issued while tile t's scores are folded into the bins,
+  // in one scheduling region.  Past the end the pipeline computes on stale LDS
+  // data whose results are never used.
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+    if (t_first + s <= t_last) load_tile<NG>(db_tiles + (int64_t)(t_first + s) * TB, lds + s * G::kLdsBytes, plan, wave, lane);
+  TileRegs<NG> fr;
+  f32x16 acc_a[NCB], acc_b[NCB];
+  if (t_last - t_first >= S - 1) wait_vmcnt<(S - 1) * G::kLoads>(); else wait_vmcnt<0>();
+  __syncthreads();
+  if (active) {
+    read_tile<NG>(fr, buf(t_first));
+    mma_tile<DT, NG, NCB>(acc_a, fr, bq, sb);
+  }
+
+  auto step = [&](int t, f32x16 (&acc_c)[NCB], f32x16 (&acc_n)[NCB]) {
+    if (t + 1 <= t_last) {
+      // tile t+1 has landed once at most min(S-2, t_last-t-1) later tiles are pending
+      if (t_last - t - 1 >= S - 2) wait_vmcnt<(S - 2) * G::kLoads>(); else wait_vmcnt<0>();
+    }
     __syncthreads();
-    if (t < t_last) load_tile<NG>(db_tiles + (t + 1) * TB, nxt);
-    if (!active) continue;
-
-    const float* auxf = reinterpret_cast<const float*>(cur + NG * 1024);
-    f32x16 init;
+    // tile t's fragments were read in the previous step: its buffer takes tile t+S
+    if (t + S <= t_last) load_tile<NG>(db_tiles + (int64_t)(t + S) * TB, buf(t), plan, wave, lane);
+    if (!active) return;
+    const int t0 = t << 5;
+    const unsigned ubase = 2u * (unsigned)t0 + 8u * (unsigned)h + 1u;  // unit of accumulator group 0
+    float nbv[NCB];
+    unsigned nbu[NCB];
+    read_tile<NG>(fr, buf(t + 1));
+    mma_tile<DT, NG, NCB>(acc_n, fr, bq, sb);
+    fast_update<NCB>(acc_c, bv, bu, nbv, nbu, ubase);
+    interleave_hint<SS::kMfma, SS::kValuPer>();
+    // materialise the update here, inside the region with the MFMAs, rather than
+    // letting the compiler sink it into the (rarely not taken) fast branch below
 #pragma unroll
-    for (int i = 0; i < 16; ++i) init[i] = auxf[h * 16 + i];
-    const int sa = cur[NG * 1024 + 128 + ql];
-    f32x16 acc[NCB];
-    MmaTile<DT, NG, NCB>::run(acc, cur, bq, init, sa, sb);
-
-    const int64_t t0 = t << 5;
-    const int64_t lo = t0 > r0 ? t0 : r0;
-    const int64_t hi = (t0 + 32) < r1 ? (t0 + 32) : r1;
-    const int t0i = (int)t0;
-    if (lo == t0 && hi == t0 + 32 && t0 + 32 <= next_start) {
-      // the whole tile lies inside the current bin
+    for (int cb = 0; cb < NCB; ++cb) asm volatile("" : "+v"(nbv[cb]), "+v"(nbu[cb]));
+    const int lo = t0 > r0 ? t0 : r0;
+    const int hi = (t0 + 32) < r1 ? (t0 + 32) : r1;
+    const bool fast = lo == t0 && hi == t0 + 32 && t0 + 32 <= next_start;  // whole tile in the current bin
+    float obv[NCB];
+    unsigned obu[NCB];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        const float before = bv[cb];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const float s = acc[cb][i];
-          const bool c = s > bv[cb];
-          bv[cb] = c ? s : bv[cb];
-          bo[cb] = c ? (8 * (i >> 2) + (i & 3)) : bo[cb];
-        }
-        bt[cb] = bv[cb] != before ? t0i : bt[cb];
-      }
+    for (int cb = 0; cb < NCB; ++cb) {  // keep the old state for the row-wise path
+      obv[cb] = bv[cb];
+      obu[cb] = bu[cb];
+      bv[cb] = fast ? nbv[cb] : bv[cb];
+      bu[cb] = fast ? nbu[cb] : bu[cb];
+    }
+    if (fast) {
       if (t0 + 32 == next_start) {  // the bin ends with this tile
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
           float mv;
-          int mi;
-          merge_halves(bv[cb], abs_index(cb), mv, mi);
+          unsigned mu;
+          merge_halves(bv[cb], bu[cb], mv, mu);
           const int64_t q = wq0 + cb * 32 + ql;
-          if (h == 0 && q < M) write_bin(outV, outA, ldo, q, cur_bin, mv, mi, sign);
+          if (h == 0 && q < M) write_bin(outV, outA, ldo, q, cur_bin, mv, mu, sign);
           bv[cb] = -INFINITY;
-          bt[cb] = kSentinel;
-          bo[cb] = 0;
+          bu[cb] = kNoUnit;
         }
         ++cur_bin;
-        next_start = bin_start(cur_bin + 1, N, L);
+        next_start = (int)bin_start(cur_bin + 1, N, L);
       }
-    } else {
-      // tile crosses a bin boundary or the chunk edge: walk its rows in order
-      int64_t cb2 = cur_bin, ns = next_start;
-#pragma unroll
-      for (int rd = 0; rd < (NCB + 1) / 2; ++rd) {
-        const int cA = 2 * rd, cB = 2 * rd + 1;
-        const bool hasB = cB < NCB;
-        float sv = -INFINITY;
-        int si = kSentinel;
-        {
-          float mv;
-          int mi;
-          merge_halves(bv[cA], abs_index(cA), mv, mi);
-          if (h == 0) { sv = mv; si = mi; }
-          if (hasB) {
-            merge_halves(bv[cB], abs_index(cB), mv, mi);
-            if (h == 1) { sv = mv; si = mi; }
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int row = 8 * (i >> 2) + 4 * h + (i & 3);
-          scratch[ql * 33 + row] = acc[cA][i];
-          if (hasB) scratch[32 * 33 + ql * 33 + row] = acc[cB][i];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const bool lane_on = (h == 0) || hasB;
-        const int64_t q = wq0 + (cA + h) * 32 + ql;
-        cb2 = cur_bin;
-        ns = next_start;
-        const float* my = scratch + h * 32 * 33 + ql * 33;
-        for (int jj = 0; jj < 32; ++jj) {
-          const int64_t j = t0 + jj;
-          if (j < lo || j >= hi) continue;
-          if (j == ns) {
-            if (lane_on && q < M) write_bin(outV, outA, ldo, q, cb2, sv, si, sign);
-            sv = -INFINITY;
-            si = kSentinel;
-            ++cb2;
-            ns = bin_start(cb2 + 1, N, L);
-          }
-          const float s = my[jj];
-          if (s > sv) { sv = s; si = (int)j; }
-        }
-        if (hi == ns) {
-          if (lane_on && q < M) write_bin(outV, outA, ldo, q, cb2, sv, si, sign);
-          sv = -INFINITY;
-          si = kSentinel;
-          ++cb2;
-          ns = cb2 < b1 ? bin_start(cb2 + 1, N, L) : r1;
-        }
-        // back to the per-half form: half 0 carries the open bin's state
-        {
-          const float vA = __shfl(sv, ql);
-          const int iA = __shfl(si, ql);
-          bv[cA] = h == 0 ? vA : -INFINITY;
-          bt[cA] = h == 0 ? iA : kSentinel;
-          bo[cA] = 0;
-          if (hasB) {
-            const float vB = __shfl(sv, 32 + ql);
-            const int iB = __shfl(si, 32 + ql);
-            bv[cB] = h == 0 ? vB : -INFINITY;
-            bt[cB] = h == 0 ? iB : kSentinel;
-            bo[cB] = 0;
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-      }
-      cur_bin = cb2;
-      next_start = ns;
+      return;
     }
+    // tile crosses a bin boundary or the chunk edge: walk its rows in order
+    int cb2 = cur_bin, ns = next_start;
+#pragma unroll
+    for (int rd = 0; rd < (NCB + 1) / 2; ++rd) {
+      const int cA = 2 * rd, cB = 2 * rd + 1;
+      const bool hasB = cB < NCB;
+      float sv = -INFINITY;
+      unsigned su = kNoUnit;
+      {
+        float mv;
+        unsigned mu;
+        merge_halves(obv[cA], obu[cA], mv, mu);
+        if (h == 0) { sv = mv; su = mu; }
+        if (hasB) {
+          merge_halves(obv[cB], obu[cB], mv, mu);
+          if (h == 1) { sv = mv; su = mu; }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int row = 8 * (i >> 2) + 4 * h + (i & 3);
+        scratch[ql * 33 + row] = acc_c[cA][i];
+        if (hasB) scratch[32 * 33 + ql * 33 + row] = acc_c[cB][i];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const bool lane_on = (h == 0) || hasB;
+      const int64_t q = wq0 + (cA + h) * 32 + ql;
+      cb2 = cur_bin;
+      ns = next_start;
+      const float* my = scratch + h * 32 * 33 + ql * 33;
+      for (int jj = 0; jj < 32; ++jj) {
+        const int j = t0 + jj;
+        if (j < lo || j >= hi) continue;
+        if (j == ns) {
+          if (lane_on && q < M) write_bin(outV, outA, ldo, q, cb2, sv, su, sign);
+          sv = -INFINITY;
+          su = kNoUnit;
+          ++cb2;
+          ns = (int)bin_start(cb2 + 1, N, L);
+        }
+        const float s = my[jj];
+        if (s > sv) { sv = s; su = 2u * (unsigned)j; }
+      }
+      if (hi == ns) {
+        if (lane_on && q < M) write_bin(outV, outA, ldo, q, cb2, sv, su, sign);
+        sv = -INFINITY;
+        su = kNoUnit;
+        ++cb2;
+        ns = cb2 < b1 ? (int)bin_start(cb2 + 1, N, L) : r1;
+      }
+      // back to the per-half form: half 0 carries the open bin's state
+      {
+        const float vA = __shfl(sv, ql);
+        const unsigned uA = __shfl(su, ql);
+        bv[cA] = h == 0 ? vA : -INFINITY;
+        bu[cA] = h == 0 ? uA : kNoUnit;
+        if (hasB) {
+          const float vB = __shfl(sv, 32 + ql);
+          const unsigned uB = __shfl(su, 32 + ql);
+          bv[cB] = h == 0 ? vB : -INFINITY;
+          bu[cB] = h == 0 ? uB : kNoUnit;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    cur_bin = cb2;
+    next_start = ns;
+  };
+  for (int t = t_first; t <= t_last; t += 2) {
+    step(t, acc_a, acc_b);
+    if (t + 1 > t_last) break;
+    step(t + 1, acc_b, acc_a);
   }
 }
 
@@ -323,9 +444,10 @@ __global__ __launch_bounds__(256) void fused_kernel(FusedParams p) {
 
 template <int DT, int NG, int NCB>
 hipError_t launch_one(const FusedParams& p, hipStream_t s) {
+  (void)hipGetLastError();  // clear any stale error so the check below sees this launch only
   const int64_t per_xcd = ceil_div(p.n_chunks, 8);
   const int64_t grid = 8 * per_xcd * p.n_qb;
-  constexpr int lb = lds_bytes<NG, NCB>();
+  constexpr int lb = lds_bytes<NG>();
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<DT, NG, NCB>),
@@ -371,8 +493,16 @@ __global__ __launch_bounds__(256) void fused_persistent_kernel(const GroupDesc* 
 
 int fused_lds_bytes(int ng, int ncb) {
   (void)ncb;
-  int per_wave = (ng * 64 + kAuxBytes / 16 + 64 * kWaves - 1) / (64 * kWaves);
-  return 2 * per_wave * 64 * kWaves * 16 + kWaves * kSlowFloats * 4;
+  switch (ng) {
+    case 2: return lds_bytes<2>();
+    case 4: return lds_bytes<4>();
+    case 6: return lds_bytes<6>();
+    case 8: return lds_bytes<8>();
+    case 12: return lds_bytes<12>();
+    case 16: return lds_bytes<16>();
+    case 24: return lds_bytes<24>();
+    default: return lds_bytes<32>();
+  }
 }
 
 #define KNN_FUSED_CASES(X)                                                                                     \
@@ -401,10 +531,11 @@ hipError_t launch_fused(int dt, int ng, int ncb, const FusedParams& p, hipStream
 }
 
 hipError_t launch_fused_persistent(int dt, const GroupDesc* d_groups, const WorkItem* d_items, int64_t n_items,
-                                   int n_blocks, int max_ng, hipStream_t s) {
+                                   int n_blocks, int lds_bytes_needed, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
   if (dt != DT_BF16) return hipErrorInvalidValue;  // the batched form is built for BF16 databases
-  const int lb = fused_lds_bytes(max_ng, 2);
+  const int lb = lds_bytes_needed;
+  (void)hipGetLastError();
   static int attr_bytes = 0;
   if (lb > attr_bytes) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_persistent_kernel<DT_BF16>),

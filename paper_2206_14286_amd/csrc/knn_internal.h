@@ -97,8 +97,9 @@ struct GroupDesc {     // all queries against one database, concatenated
   int64_t ldo;
   int32_t ng, ncb;
 };
+// lds_bytes_needed: the largest fused_lds_bytes() over the groups the items touch
 hipError_t launch_fused_persistent(int dt, const GroupDesc* d_groups, const WorkItem* d_items, int64_t n_items,
-                                   int n_blocks, int max_ng, hipStream_t s);
+                                   int n_blocks, int lds_bytes_needed, hipStream_t s);
 
 // ---- exact top-K over candidate lists (ExactRescoring)
 // row r: candidates V[r*ldv + c], A[r*ldv + c] for c < n, in the metric's own sign.
@@ -115,8 +116,19 @@ struct SelRow {
   int32_t minimize;
   float* out_val;
   int32_t* out_idx;
+  // for resolving 4-row group winners of this row's output
+  const unsigned char* q_tiles;
+  const unsigned char* db_tiles;
+  int64_t q_row;
+  int32_t ng, pad_;
 };
 hipError_t launch_select_rows(const SelRow* d_rows, int64_t rows, int max_K, hipStream_t s);
+
+// ---- exact rows for bin winners recorded as 4-row groups (codes <= -2, see
+// knn_fused.hip): codes[i*ld + c] for i < rows, c < cols, query i of q_tiles
+hipError_t launch_resolve(int dt, int32_t* codes, int64_t rows, int64_t cols, int64_t ld,
+                          const unsigned char* q_tiles, const unsigned char* db_tiles, int ng, hipStream_t s);
+hipError_t launch_resolve_rows(int dt, const SelRow* d_rows, int64_t rows, hipStream_t s);
 
 // ---- FP32 rerank of Kr candidates per query from the original rows
 hipError_t launch_rerank(const int32_t* cand, int64_t M, int Kr, const void* Q, int q_dt, const void* X,

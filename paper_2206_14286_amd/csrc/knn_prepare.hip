@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void prepare_segments_kernel(const QSeg* segs,
 hipError_t launch_prepare(const void* src, int in_dt, int64_t rows, int D, int metric, int compute,
                           bool database, unsigned char* tiles, int64_t n_tiles, float* orig_half_norm,
                           float* orig_rnorm, hipStream_t s) {
+  (void)hipGetLastError();  // report only this call's launch errors
   const int ng = groups_for(dpad_for(D, compute), compute);
   const int64_t n = n_tiles * kTileRows;
   if (n == 0) return hipSuccess;
@@ -146,6 +147,7 @@ hipError_t launch_prepare(const void* src, int in_dt, int64_t rows, int D, int m
 
 hipError_t launch_prepare_segments(const QSeg* d_segs, int nseg, int64_t total_rows, int in_dt, int compute,
                                    hipStream_t s) {
+  (void)hipGetLastError();  // report only this call's launch errors
   if (total_rows == 0 || nseg == 0) return hipSuccess;
   const unsigned grid = (unsigned)ceil_div(total_rows, 256);
   if (compute == DT_F32)

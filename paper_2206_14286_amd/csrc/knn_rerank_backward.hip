@@ -209,6 +209,7 @@ __global__ __launch_bounds__(256) void backward_dx_kernel(const float* __restric
 hipError_t launch_rerank(const int32_t* cand, int64_t M, int Kr, const void* Q, int q_dt, const void* X, int x_dt,
                          int D, int metric, const float* x_half_norm, const float* x_rnorm, int K, float* out_val,
                          int32_t* out_idx, hipStream_t s) {
+  (void)hipGetLastError();  // report only this call's launch errors
   if (M == 0) return hipSuccess;
   if (Kr > kRerankMaxKr || K > Kr || D > 256) return hipErrorInvalidValue;
   const int64_t grid = M < 65536 ? M : 65536;
@@ -219,6 +220,7 @@ hipError_t launch_rerank(const int32_t* cand, int64_t M, int Kr, const void* Q, 
 
 hipError_t launch_backward(const float* g, const int32_t* idx, const void* Q, const void* X, int dt, int64_t M,
                            int64_t N, int D, int K, int metric, float* dQ, float* dX, hipStream_t s) {
+  (void)hipGetLastError();  // report only this call's launch errors
   if (M == 0) return hipSuccess;
   if (D > 256) return hipErrorInvalidValue;
   if (dQ) {

@@ -7,7 +7,8 @@
 // best score T exactly; if T is shared by more rows than are still needed, a
 // second radix select on the row indices keeps the lowest ones.  The K survivors
 // are then bitonic-sorted in LDS by (score, lower index first) and written best
-// first.  Cost per row: O(L) reads per pass instead of O(L log^2 L).
+// first.  Cost per row: O(L) reads per pass instead of O(L log^2 L).  Candidates
+// may still be 4-row group codes; they keep their code (resolved afterwards).
 #include "knn_common.cuh"
 
 namespace knn {
@@ -16,6 +17,21 @@ namespace {
 
 constexpr int kSelThreads = 256;
 constexpr int kMaxK = 1024;
+
+// Candidate indices are rows (>= 0), 4-row group codes (-2 - start/4, resolved
+// later) or -1 (none).  The tie-break key orders them by row: unit u = 2*start +
+// is_group is unique per candidate (bins are disjoint), and the sort uses ~u so
+// that a lower row ranks first; "none" maps to 0, below every real unit.
+__device__ __forceinline__ unsigned unit_lo(int32_t code) {
+  if (code >= 0) return ~(2u * (unsigned)code);
+  if (code == -1) return 0u;
+  return ~(2u * 4u * (unsigned)(-2 - code) + 1u);
+}
+__device__ __forceinline__ int32_t unit_code(unsigned lo) {
+  if (lo == 0u) return -1;
+  const unsigned u = ~lo;
+  return (u & 1u) ? -2 - (int32_t)(u >> 3) : (int32_t)(u >> 1);
+}
 
 struct SelShared {
   unsigned hist[256];
@@ -100,7 +116,7 @@ __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int
     int kr2 = krem, eq2 = 0;
     auto ikey = [&](int64_t c, bool& ok) {
       ok = float_key(sgn * V[c]) == T;
-      return ~(unsigned)A[c];
+      return unit_lo(A[c]);
     };
     for (int shift = 24; shift >= 0; shift -= 8) {
       radix_pass(sh, n, ikey, p2, m2, shift, kr2, d2, eq2);
@@ -114,7 +130,7 @@ __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int
   __syncthreads();
   for (int64_t c = tid; c < n; c += kSelThreads) {
     const unsigned k = float_key(sgn * V[c]);
-    const unsigned lo = ~(unsigned)A[c];
+    const unsigned lo = unit_lo(A[c]);
     const bool take = (k > T) || (k == T && (all_eq || lo >= T2));
     if (take) {
       int pos = atomicAdd(&sh.count, 1);
@@ -147,7 +163,7 @@ __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int
     const unsigned long long key = sh.keys[i];
     float v = key_float((unsigned)(key >> 32));
     out_val[i] = sgn * v;
-    out_idx[i] = (int32_t)~(unsigned)(key & 0xFFFFFFFFull);
+    out_idx[i] = unit_code((unsigned)(key & 0xFFFFFFFFull));
   }
   __syncthreads();
 }
@@ -175,6 +191,7 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(const SelRow* 
 
 hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t n, int64_t ldv, int K,
                          bool minimize, float* out_val, int32_t* out_idx, int64_t ldout, hipStream_t s) {
+  (void)hipGetLastError();  // report only this call's launch errors
   if (rows == 0) return hipSuccess;
   if (K > kMaxK || K < 1 || n < 1) return hipErrorInvalidValue;
   const int64_t grid = rows < 65536 ? rows : 65536;
@@ -184,6 +201,7 @@ hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t
 }
 
 hipError_t launch_select_rows(const SelRow* d_rows, int64_t rows, int max_K, hipStream_t s) {
+  (void)hipGetLastError();  // report only this call's launch errors
   if (rows == 0) return hipSuccess;
   if (max_K > kMaxK) return hipErrorInvalidValue;
   const int64_t grid = rows < 65536 ? rows : 65536;

@@ -63,6 +63,7 @@ def lib():
             "knn_query_buffer_bytes": (ctypes.c_size_t, [P, i64]),
             "knn_query_prepare": (i32, [P, P, i32, i64, P, ctypes.c_size_t, P]),
             "knn_partial_reduce": (i32, [P, P, i64, i64, P, P, P]),
+            "knn_resolve_rows": (i32, [P, P, i64, i64, P, i64, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -205,14 +206,18 @@ class Database:
         _check(lib().knn_query_prepare(self._h, _ptr(Q), _in_dtype(Q), M, _ptr(buf), nbytes, _stream()))
         return buf
 
-    def partial_reduce(self, qbuf: torch.Tensor, M: int, L: int, out=None):
-        """``knn_partial_reduce`` (Algorithm 1 alone): bin winners (values, indices), M x L."""
+    def partial_reduce(self, qbuf: torch.Tensor, M: int, L: int, out=None, resolve: bool = True):
+        """``knn_partial_reduce`` (Algorithm 1 alone): bin winners (values, indices), M x L.
+        With ``resolve`` the compact 4-row group entries are replaced by exact rows
+        (``knn_resolve_rows``)."""
         if out is None:
             bv = torch.empty((M, L), dtype=torch.float32, device=qbuf.device)
             bi = torch.empty((M, L), dtype=torch.int32, device=qbuf.device)
         else:
             bv, bi = out
         _check(lib().knn_partial_reduce(self._h, _ptr(qbuf), int(M), int(L), _ptr(bv), _ptr(bi), _stream()))
+        if resolve:
+            _check(lib().knn_resolve_rows(self._h, _ptr(qbuf), int(M), int(L), _ptr(bi), int(L), _stream()))
         return bv, bi
 
 
