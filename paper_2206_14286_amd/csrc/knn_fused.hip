@@ -27,6 +27,8 @@
 //     lane halves are merged).
 //   * Workgroup ids are mapped so that the workgroups running on one XCD at a
 //     time share the same bin chunk, and its tiles are served from that XCD's L2.
+#include <type_traits>
+
 #include "knn_common.cuh"
 
 namespace knn {
@@ -116,12 +118,12 @@ template <int NG>
 __device__ __forceinline__ void read_tile(TileRegs<NG>& r, const unsigned char* tile) {
   using G = TileGeom<NG>;
   const int lane = threadIdx.x & 63, h = lane >> 5;
-#pragma unroll
-  for (int g = 0; g < NG; ++g) r.af[g] = *reinterpret_cast<const u32x4*>(tile + g * 1024 + lane * 16);
   const float* auxf = reinterpret_cast<const float*>(tile + G::kMainBytes);
 #pragma unroll
   for (int i = 0; i < 16; ++i) r.init[i] = auxf[h * 16 + i];
   r.sa = tile[G::kMainBytes + 128 + (lane & 31)];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) r.af[g] = *reinterpret_cast<const u32x4*>(tile + g * 1024 + lane * 16);
 }
 
 // acc[cb] = init + sum over the tile depth of A(tile rows) x B(query columns)
@@ -168,6 +170,60 @@ __device__ __forceinline__ void mma_tile(f32x16 (&acc)[NCB], const TileRegs<NG>&
   }
 }
 
+// The matrix instructions of one tile, in fixed order (one k-step for every column
+// block, then the next k-step), with the U = 4*NCB units of the previous tile's
+// bin update spread evenly between them.  A full scheduling barrier after each
+// group pins the order: every unit's VALU instructions issue while the matrix
+// unit is busy with the group just issued, and alternating column blocks keeps
+// consecutive matrix instructions independent.
+// Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).  Used where
+// the body indexes register arrays, so that no trip-count heuristic can leave a
+// loop rolled and move the arrays to scratch memory.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+template <int DT, int NG, int NCB, class UnitFn>
+__device__ __forceinline__ void mma_tile_interleaved(f32x16 (&acc)[NCB], const TileRegs<NG>& r,
+                                                     const u32x4 (&bq)[NCB][NG], const int (&sb)[NCB],
+                                                     UnitFn&& unit) {
+  constexpr int P = DT == DT_FP8 ? NG / 2 : (DT == DT_BF16 ? NG : 4 * NG);  // k-steps per column block
+  constexpr int U = 4 * NCB;
+  static_for<0, P>([&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    static_for<0, NCB>([&](auto cc) {
+      constexpr int cb = decltype(cc)::value;
+      if constexpr (DT == DT_FP8) {
+        const u32x4& a0 = r.af[2 * s];
+        const u32x4& a1 = r.af[2 * s + 1];
+        const u32x4& b0 = bq[cb][2 * s];
+        const u32x4& b1 = bq[cb][2 * s + 1];
+        i32x8 A = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+        i32x8 B = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+        acc[cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, B, s == 0 ? r.init : acc[cb], 0, 0, 0, r.sa, 0,
+                                                                   sb[cb]);
+      } else if constexpr (DT == DT_BF16) {
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, r.af[s]),
+                                                          __builtin_bit_cast(bf16x8, bq[cb][s]),
+                                                          s == 0 ? r.init : acc[cb], 0, 0, 0);
+      } else {
+        constexpr int g = s >> 2, e = s & 3;
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(r.af[g][e]), __uint_as_float(bq[cb][g][e]),
+                                                       s == 0 ? r.init : acc[cb], 0, 0, 0);
+      }
+    });
+    static_for<0, U>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      if constexpr (u * P / U == s) unit(uc);
+    });
+    __builtin_amdgcn_sched_barrier(0);
+  });
+}
+
 // A bin's running winner is a "unit": either one exact row or a group of 4
 // consecutive rows (one lane's accumulators 4k..4k+3) whose exact row is resolved
 // later from the prepared rows.  Units are keyed u = 2*start + is_group (unsigned,
@@ -193,58 +249,12 @@ __device__ __forceinline__ void write_bin(float* __restrict__ outV, int32_t* __r
   outA[q * ldo + bin] = code;
 }
 
-// scheduling hint for one pipelined step: the LDS reads of the next tile's
-// fragments go first, then each matrix instruction of the next tile alternates
-// with a few VALU instructions of the current tile's bin update, so the reads'
-// latency and the bin update both hide behind the matrix unit inside one wave
-template <int N, int V>
-__device__ __forceinline__ void interleave_hint() {
-  if constexpr (N > 0) {
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
-    __builtin_amdgcn_sched_group_barrier(0x002, V, 0);  // VALU
-    interleave_hint<N - 1, V>();
-  }
-}
-
-template <int DT, int NG, int NCB>
-struct StepShape {
-  static constexpr int kMfma = DT == DT_FP8 ? (NG / 2) * NCB : (DT == DT_BF16 ? NG * NCB : 4 * NG * NCB);
-  static constexpr int kValu = 24 * NCB;  // fast bin update: ~5 per 4 scores + unit arithmetic
-  static constexpr int kValuPer = (kValu + kMfma - 1) / kMfma;
-};
-
-// The fast bin update of one tile (every row of the tile in the current bin): per
-// lane the max of each group of 4 accumulators (rows t0 + 8k + 4h + 0..3), compared
-// with the running best in row order; returns the updated state in nbv/nbu.
-template <int NCB>
-__device__ __forceinline__ void fast_update(const f32x16 (&acc)[NCB], const float (&bv)[NCB],
-                                            const unsigned (&bu)[NCB], float (&nbv)[NCB], unsigned (&nbu)[NCB],
-                                            unsigned ubase) {
-#pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) {
-    nbv[cb] = bv[cb];
-    nbu[cb] = bu[cb];
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const float gk =
-          fmaxf(fmaxf(fmaxf(acc[cb][4 * k], acc[cb][4 * k + 1]), acc[cb][4 * k + 2]), acc[cb][4 * k + 3]);
-      const bool c = gk > nbv[cb];
-      nbv[cb] = c ? gk : nbv[cb];
-      nbu[cb] = c ? ubase + 16u * k : nbu[cb];
-    }
-  }
-}
-
 template <int DT, int NG, int NCB>
 __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_tiles,
                                          const unsigned char* __restrict__ q_tiles, int64_t N, int64_t L, int64_t M,
                                          int64_t q0, int64_t b0, int64_t b1, float sign, float* __restrict__ outV,
                                          int32_t* __restrict__ outA, int64_t ldo, unsigned char* lds) {
   using G = TileGeom<NG>;
-  using SS = StepShape<DT, NG, NCB>;
   constexpr int S = G::kStages;
   static_assert((S & (S - 1)) == 0 && S >= 2, "stages: a power of two >= 2");
   constexpr int64_t TB = (int64_t)NG * 1024 + kAuxBytes;
@@ -313,10 +323,24 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     const unsigned ubase = 2u * (unsigned)t0 + 8u * (unsigned)h + 1u;  // unit of accumulator group 0
     float nbv[NCB];
     unsigned nbu[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      nbv[cb] = bv[cb];
+      nbu[cb] = bu[cb];
+    }
     read_tile<NG>(fr, buf(t + 1));
-    mma_tile<DT, NG, NCB>(acc_n, fr, bq, sb);
-    fast_update<NCB>(acc_c, bv, bu, nbv, nbu, ubase);
-    interleave_hint<SS::kMfma, SS::kValuPer>();
+    __builtin_amdgcn_sched_barrier(0);
+    // unit u: accumulator group k = u / NCB (rows t0 + 8k + 4h + 0..3) of column block
+    // cb = u % NCB of tile t, against the running best (groups in row order)
+    mma_tile_interleaved<DT, NG, NCB>(acc_n, fr, bq, sb, [&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      constexpr int k = u / NCB, cb = u % NCB;
+      const float gk = fmaxf(fmaxf(fmaxf(acc_c[cb][4 * k], acc_c[cb][4 * k + 1]), acc_c[cb][4 * k + 2]),
+                             acc_c[cb][4 * k + 3]);
+      const bool c = gk > nbv[cb];
+      nbv[cb] = c ? gk : nbv[cb];
+      nbu[cb] = c ? ubase + 16u * k : nbu[cb];
+    });
     // materialise the update here, inside the region with the MFMAs, rather than
     // letting the compiler sink it into the (rarely not taken) fast branch below
 #pragma unroll
