@@ -264,6 +264,25 @@ def recall_tie_aware(retrieved_scores, kth_best, minimize: bool) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------------------
+# performance model (Sec. Methodology: eq. roofline, eq. c-limit; Sec. Algorithm: eq. pr:icop)
+# ----------------------------------------------------------------------------------------
+def cop_budget(D: int, pi_tflops: float, gamma_tcops: float) -> float:
+    """eq. c-limit: the most COPs per score that keep the COP roofline above the
+    matrix peak, C <= 2 D gamma / pi."""
+    return 2.0 * D * gamma_tcops / pi_tflops
+
+
+def cop_intensity(D: int, C: float) -> float:
+    """eq. pr:icop: FLOPs per COP of the bin-reduce kernel, I_COP = 2D / C."""
+    return 2.0 * D / C
+
+
+def roofline_gflops(pi_tflops: float, beta_gbs: float, gamma_tcops: float, i_mem: float, i_cop: float) -> float:
+    """eq. roofline: attainable GFLOP/s = min(pi, beta * I_MEM, gamma * I_COP)."""
+    return min(pi_tflops * 1e3, beta_gbs * i_mem, gamma_tcops * 1e3 * i_cop)
+
+
+# ----------------------------------------------------------------------------------------
 # reference quantisers, written from the definitions of the formats
 # ----------------------------------------------------------------------------------------
 def bf16_round(x):

@@ -60,6 +60,17 @@ __device__ __forceinline__ void wait_vmcnt() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
+// Word 3 of a raw buffer descriptor on gfx9-family parts: 32-bit data format, no
+// swizzle, no index stride (byte-addressed raw loads).
+constexpr int kBufferWord3 = 0x00020000;
+
+// Workgroup barrier without the memory fence __syncthreads() implies.  The fence
+// would make the compiler wait for every outstanding direct-to-LDS tile load at
+// each barrier, draining the copy pipeline; instead each wave waits explicitly for
+// its own loads of the tile about to be read (wait_vmcnt) before the barrier, and
+// the asm's memory clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
 // Per-lane byte offsets of the 16-byte pieces a lane moves when a tile is copied
 // into LDS; the same for every tile of an item, so they are computed once and the
 // loads use a uniform tile base plus these offsets.
@@ -83,25 +94,31 @@ __device__ __forceinline__ TileLoadPlan<NG> make_load_plan(int wave, int lane) {
 }
 
 // copy one prepared tile (NG KiB of fragments + 256 B aux) into LDS with direct
-// global->LDS loads.  Every wave issues the same number of loads (kLoads): pieces
+// buffer->LDS loads.  Every wave issues the same number of loads (kLoads): pieces
 // past the end re-read the last fragment piece and land in the buffer's pad, and
 // each wave moves a quarter of the aux block with four lanes, so per-wave vmcnt
 // counts are uniform and a tile's arrival can be awaited with one immediate.
 // `wave` must be wave-uniform (an SGPR value): the LDS destination of each load is.
+// The buffer form (rather than the flat-encoded global form) matters: the compiler
+// counts a flat-encoded LDS load as a possibly out-of-order LDS event and then
+// waits for all LDS reads at the first use of any, while after buffer loads it
+// waits per fragment.  The descriptor covers exactly the tile (bounds-checked).
 template <int NG>
 __device__ __forceinline__ void load_tile(const unsigned char* __restrict__ src, unsigned char* lds_dst,
                                           const TileLoadPlan<NG>& p, int wave, int lane) {
   using G = TileGeom<NG>;
+  const auto rsrc =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<unsigned char*>(src), 0, (int)tile_bytes(NG), kBufferWord3);
 #pragma unroll
   for (int it = 0; it < G::kPerWave; ++it) {
     unsigned char* dst = lds_dst + (it * 64 * kWaves + wave * 64) * 16;
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + p.frag_off[it]),
-                                     (__attribute__((address_space(3))) void*)(dst), 16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(dst), 16, (int)p.frag_off[it],
+                                             0, 0, 0);
   }
   if (lane < 4) {
     unsigned char* dst = lds_dst + G::kMainBytes + wave * 64;
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + p.aux_off),
-                                     (__attribute__((address_space(3))) void*)(dst), 16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void*)(dst), 16, (int)p.aux_off, 0,
+                                             0, 0);
   }
 }
 
@@ -304,7 +321,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   TileRegs<NG> fr;
   f32x16 acc_a[NCB], acc_b[NCB];
   if (t_last - t_first >= S - 1) wait_vmcnt<(S - 1) * G::kLoads>(); else wait_vmcnt<0>();
-  __syncthreads();
+  lds_barrier();
   if (active) {
     read_tile<NG>(fr, buf(t_first));
     mma_tile<DT, NG, NCB>(acc_a, fr, bq, sb);
@@ -315,7 +332,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       // tile t+1 has landed once at most min(S-2, t_last-t-1) later tiles are pending
       if (t_last - t - 1 >= S - 2) wait_vmcnt<(S - 2) * G::kLoads>(); else wait_vmcnt<0>();
     }
-    __syncthreads();
+    lds_barrier();
     // tile t's fragments were read in the previous step: its buffer takes tile t+S
     if (t + S <= t_last) load_tile<NG>(db_tiles + (int64_t)(t + S) * TB, buf(t), plan, wave, lane);
     if (!active) return;
