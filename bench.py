@@ -66,9 +66,10 @@ def time_kernel_events(fn, reps):
     return s.elapsed_time(e) / reps / 1e3
 
 
-def run_variant(knn, Xd, Qd, w, compute, rerank, steps, warmup, sample_idx):
+def run_variant(knn, Xd, Qd, w, compute, rerank, steps, warmup, sample_idx, L=None):
     import torch
-    M, N, D, K, L = Qd.shape[0], Xd.shape[0], w["D"], w["K"], w["L"]
+    M, N, D, K = Qd.shape[0], Xd.shape[0], w["D"], w["K"]
+    L = w["L"] if L is None else L
     t0 = time.perf_counter()
     db = knn.Database(Xd, w["metric"], compute)
     prep_s = time.perf_counter() - t0
@@ -85,6 +86,7 @@ def run_variant(knn, Xd, Qd, w, compute, rerank, steps, warmup, sample_idx):
     flops = 2.0 * M * N * dpad(D, compute)
     res = {
         "compute": compute,
+        "L": L,
         "rerank_k": rerank,
         "ms_per_step": sec * 1e3,
         "queries_per_s": M / sec,
@@ -100,6 +102,136 @@ def run_variant(knn, Xd, Qd, w, compute, rerank, steps, warmup, sample_idx):
     return res
 
 
+# --------------------------------------------------------------------------- other workloads
+def kernel_frac(flops, sec, compute):
+    return {"tflops": flops / sec / 1e12, "frac_of_peak": flops / sec / 1e12 / PEAK_TFLOPS[compute]}
+
+
+def row_mips_small(torch, knn, datagen, reps=200):
+    """Plain FP32 entry point (knn_search) on the small MIPS workload: microseconds per call
+    (database preparation included, as the plain entry point takes raw FP32 rows)."""
+    w = datagen.WORKLOADS["mips_small"]
+    Q, X = datagen.make("mips_small", seed=0)
+    Qd, Xd = torch.from_numpy(Q).cuda(), torch.from_numpy(X).cuda()
+    K, L = w["K"], w["L"]
+    sec = time_kernel_events(lambda: knn.search(Qd, Xd, K, L, "mips"), reps)
+    M, N = Q.shape[0], X.shape[0]
+    return {"workload": "mips_small", "M": M, "N": N, "D": w["D"], "K": K, "L": L, "compute": "fp32",
+            "us_per_call": sec * 1e6, "queries_per_s": M / sec, **kernel_frac(2.0 * M * N * 128, sec, "fp32")}
+
+
+def row_cosine_glove(torch, knn, datagen, oracle, steps, warmup, sample_n=16):
+    """GloVe-shaped cosine search (K = 100, L = 16,384): FP32 plain against FP8 + FP32 rerank,
+    the rerank depth raised until the FP8 form's recall reaches the FP32 form's."""
+    w = datagen.WORKLOADS["cosine_glove"]
+    Q, X = datagen.make("cosine_glove", seed=0)
+    Qd, Xd = torch.from_numpy(Q).cuda(), torch.from_numpy(X).cuda()
+    M, N, D, K, L = Q.shape[0], X.shape[0], w["D"], w["K"], w["L"]
+    sample = np.sort(np.random.default_rng(3).choice(M, sample_n, replace=False))
+    st = torch.from_numpy(sample).cuda()
+    log("cosine_glove: oracle exact on", sample_n, "queries")
+    ex = oracle.search(Q[sample], X, "cosine", L, K, exact=True)
+    kth = ex["ex_v"][:, -1]
+
+    def recall_of(idx):
+        s64, _ = oracle.pair_scores(Q[sample], X, "cosine", np.repeat(np.arange(sample_n), K), idx.ravel())
+        return float(oracle.recall_tie_aware(s64.reshape(-1, K), kth, False).mean())
+
+    out = {"workload": "cosine_glove", "M": M, "N": N, "D": D, "K": K, "L": L,
+           "oracle_fp64_recall_tie_aware": float(oracle.recall_tie_aware(ex["top_v"], kth, False).mean())}
+    o = (torch.empty((M, K), dtype=torch.float32, device="cuda"), torch.empty((M, K), dtype=torch.int32, device="cuda"))
+    bins = (torch.empty((M, L), dtype=torch.float32, device="cuda"), torch.empty((M, L), dtype=torch.int32, device="cuda"))
+    for compute in ("fp32", "fp8"):
+        db = knn.Database(Xd, "cosine", compute)
+        rr = 0
+        if compute == "fp8":
+            for rr in (K, 2 * K, 3 * K, 4 * K, 6 * K, 8 * K):
+                rec = recall_of(db.search(Qd[st], K, L, rerank=rr)[1].cpu().numpy())
+                log(f"  fp8 rerank {rr}: recall {rec:.4f}")
+                if rec >= out["fp32"]["recall_tie_aware"]:
+                    break
+        sec = time_steps(lambda: db.search(Qd, K, L, rerank=rr, out=o), steps, warmup)
+        rec = recall_of(o[1][st].cpu().numpy())
+        qbuf = db.prepare_queries(Qd)
+        ksec = time_kernel_events(lambda: db.partial_reduce(qbuf, M, L, out=bins, resolve=False), max(steps, 3))
+        out[compute] = {"rerank_k": rr, "ms_per_step": sec * 1e3, "queries_per_s": M / sec,
+                        "recall_tie_aware": rec, "fused_kernel_ms": ksec * 1e3,
+                        **kernel_frac(2.0 * M * N * dpad(D, compute), ksec, compute)}
+        log(f"  cosine_glove {compute}: {out[compute]}")
+        del db, qbuf
+        torch.cuda.empty_cache()
+    return out
+
+
+def row_batched(torch, knn, datagen, steps):
+    """256 query batches (log-uniform sizes in [1, 4096]) against four BF16 databases in one
+    persistent launch, replayed from a captured graph.  Roofline: per database the larger
+    of its MFMA time and one read of its rows, summed."""
+    bf16 = torch.bfloat16
+    xs = [datagen.normal_device(n, d, seed=1000 + i, dtype=bf16) for i, (n, d) in enumerate(datagen.BATCHED_DBS)]
+    dbs = [knn.Database(x, "mips", "bf16") for x in xs]
+    sizes = datagen.batch_sizes(datagen.BATCHED_COUNT, seed=2)
+    batches = []
+    for b, m in enumerate(sizes):
+        d = b % len(dbs)
+        batches.append((datagen.normal_device(int(m), datagen.BATCHED_DBS[d][1], seed=2000 + b, dtype=bf16), d, 10))
+    t0 = time.perf_counter()
+    plan = knn.BatchedPlan(dbs, batches, recall_target=0.95, tune=False)
+    create_s = time.perf_counter() - t0
+    plan.run()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.run()
+    sec = time_steps(graph.replay, steps, 1)
+    info = plan.info()
+    bound = 0.0
+    flops = 0.0
+    for d, (n, dd) in enumerate(datagen.BATCHED_DBS):
+        f = sum(2.0 * int(m) * n * dpad(dd, "bf16") for b, m in enumerate(sizes) if b % len(dbs) == d)
+        flops += f
+        bound += max(f / (PEAK_TFLOPS["bf16"] * 1e12), n * dpad(dd, "bf16") * 2 / (HBM_GBS * 1e9))
+    nq = int(sizes.sum())
+    del graph, plan, dbs, xs, batches
+    torch.cuda.empty_cache()
+    return {"workload": "batched", "batches": len(sizes), "queries": nq, "databases": datagen.BATCHED_DBS,
+            "plan": info, "plan_create_s": create_s, "ms_per_run": sec * 1e3, "queries_per_s": nq / sec,
+            "tflops": flops / sec / 1e12, "roofline_bound_ms": bound * 1e3, "frac_of_roofline": bound / sec}
+
+
+def row_mips_backward(torch, knn, datagen, steps):
+    """Forward BF16 search (K = 64, L = 32,768) and the backward of a softmax cross-entropy over
+    the retrieved scores (random target per query): dQ gather and dX scatter-add."""
+    w = datagen.WORKLOADS["mips_backward"]
+    M, N, D, K, L = w["M"], w["N"], w["D"], w["K"], w["L"]
+    bf16 = torch.bfloat16
+    s = 1.0 / D ** 0.5
+    X = datagen.normal_device(N, D, seed=3000, scale=s, dtype=bf16)
+    Q = datagen.normal_device(M, D, seed=3001, scale=s, dtype=bf16)
+    db = knn.Database(X, "mips", "bf16")
+    o = (torch.empty((M, K), dtype=torch.float32, device="cuda"), torch.empty((M, K), dtype=torch.int32, device="cuda"))
+    fsec = time_steps(lambda: db.search(Q, K, L, out=o), steps, 1)
+    vals, idx = o
+    t = torch.from_numpy(datagen.targets(M, K, seed=2)).cuda()
+    g = torch.softmax(vals, dim=1)
+    g[torch.arange(M, device="cuda"), t] -= 1.0
+    g = (g / M).contiguous()
+    dQ = torch.empty((M, D), dtype=torch.float32, device="cuda")
+    dX = torch.zeros((N, D), dtype=torch.float32, device="cuda")
+    bsec = time_steps(lambda: knn.backward(g, idx, Q, X, "mips", out=(dQ, dX)), steps, 1)
+    gathered = M * K * D * 2.0 * 2  # X rows for dQ and Q rows for dX, BF16
+    atomics = M * K * D
+    res = {"workload": "mips_backward", "M": M, "N": N, "D": D, "K": K, "L": L,
+           "forward_ms": fsec * 1e3, "forward_queries_per_s": M / fsec,
+           **{"forward_" + k: v for k, v in kernel_frac(2.0 * M * N * D, fsec, "bf16").items()},
+           "backward_ms": bsec * 1e3, "backward_atomics_per_s": atomics / bsec,
+           "backward_gb_s": (gathered + atomics * 4.0) / bsec / 1e9,
+           "backward_frac_of_hbm": (gathered + atomics * 4.0) / bsec / 1e9 / HBM_GBS}
+    del db, X, Q, dX, dQ
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +243,8 @@ def main():
     ap.add_argument("--recall-sample", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rows", default="fp8_equal_recall,mips_small,cosine_glove,batched,mips_backward",
+                    help="other measurements to add to the line (empty: none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size kernel for "
                          "scaling hardware byte counters)")
@@ -196,6 +330,39 @@ def main():
         },
         "variants": {k: v for k, v in results.items() if k != args.compute},
     }
+    rows = [r for r in args.rows.split(",") if r]
+    if "fp8_equal_recall" in rows and "fp32" in results:
+        # FP8 + rerank at the FP32 form's recall: more bins (a bin's FP8 winner may be the
+        # wrong row of the bin; smaller bins hold fewer rivals) and a deeper rerank
+        target = results["fp32"]["recall_at_10_tie_aware"]
+        pick = None
+        db8 = knn.Database(Xd, w["metric"], "fp8")
+        for L8, Kr8 in ((L, 40), (2 * L, 64), (4 * L, 100), (8 * L, 160), (16 * L, 256)):
+            idx8 = db8.search(Qd[sample_t], K, L8, rerank=Kr8)[1].cpu().numpy()
+            s64, _ = oracle.pair_scores(Q[sample], X, w["metric"], np.repeat(np.arange(len(sample)), K), idx8.ravel())
+            rec = float(oracle.recall_tie_aware(s64.reshape(-1, K), kth, True).mean())
+            log(f"fp8 L={L8} rerank={Kr8}: recall {rec:.4f} (target {target:.4f})")
+            pick = (L8, Kr8, rec)
+            if rec >= target:
+                break
+        del db8
+        torch.cuda.empty_cache()
+        r8 = run_variant(knn, Xd, Qd, w, "fp8", pick[1], args.steps, args.warmup, sample_t, L=pick[0])
+        del r8["idx_sample"], r8["val_sample"]
+        r8["recall_at_10_tie_aware"] = pick[2]
+        r8["target_recall"] = target
+        line["fp8_equal_recall"] = r8
+    others = {}
+    for name_r, fn in (("mips_small", lambda: row_mips_small(torch, knn, datagen)),
+                       ("cosine_glove", lambda: row_cosine_glove(torch, knn, datagen, oracle, 5, 1)),
+                       ("batched", lambda: row_batched(torch, knn, datagen, 3)),
+                       ("mips_backward", lambda: row_mips_backward(torch, knn, datagen, 3))):
+        if name_r in rows:
+            log("workload", name_r)
+            others[name_r] = fn()
+            log(" ", json.dumps(others[name_r]))
+    if others:
+        line["other_workloads"] = others
     if not args.no_cpu:
         threads = len(os.sched_getaffinity(0))
         log("cpu baseline: oracle on", threads, "threads")

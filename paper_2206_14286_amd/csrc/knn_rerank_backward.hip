@@ -2,9 +2,9 @@
 // backward pass through the retrieved scores.
 //
 // Rerank: the distance kernel ranks bins with BF16 or FP8 products; the best Kr
-// bin winners are rescored here in FP32 from the caller's original rows, one
-// workgroup per query (lanes split the depth, a fixed butterfly sums the lanes),
-// and the best K by (score, lower index) are kept with an LDS bitonic sort.
+// bin winners are rescored here in FP32 from the caller's original rows, one wave
+// per query (16-lane groups per candidate, a fixed butterfly sums the pieces), and
+// the best K by (score, lower index) are kept with a register bitonic sort.
 //
 // Backward: with the selection held fixed, d score(q_i, x_j) is a gather over the
 // selected rows for dQ (one wave per query) and a scatter-add into dX (one wave
@@ -15,7 +15,7 @@ namespace knn {
 
 namespace {
 
-constexpr int kRerankThreads = 256;
+constexpr int kRerankThreads = 256;  // 4 waves, one query each
 constexpr int kRerankMaxKr = 1024;
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -24,6 +24,52 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
+  const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, m), hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), m);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sort 64*R keys held by one wave (element e = 64*r + lane) in descending order:
+// a bitonic network whose exchanges within a lane's registers are plain compares
+// and whose exchanges across lanes are shuffles.
+template <int R>
+__device__ __forceinline__ void wave_sort_desc(unsigned long long (&k)[R], int lane) {
+  constexpr int N = 64 * R;
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= 64) {
+        const int rs = stride >> 6;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (r & rs) continue;  // handle each in-lane pair once, from its lower element
+          const int e = 64 * r + lane;
+          const bool desc = (e & size) == 0;
+          const unsigned long long a = k[r], b = k[r | rs];
+          const bool sw = desc ? (a < b) : (a > b);
+          k[r] = sw ? b : a;
+          k[r | rs] = sw ? a : b;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int e = 64 * r + lane;
+          const bool desc = (e & size) == 0, lower = (e & stride) == 0;
+          const unsigned long long o = shfl_xor_u64(k[r], stride);
+          const bool take_max = desc == lower;
+          k[r] = take_max ? (o > k[r] ? o : k[r]) : (o < k[r] ? o : k[r]);
+        }
+      }
+    }
+  }
+}
+
+// One wave per query.  Candidate scores: groups of 16 lanes each take a candidate
+// row and split its depth into 16-byte pieces (4 FP32 or 8 BF16 elements per lane
+// per pass); a fixed 16-lane butterfly sums the pieces.  Keys (score, lower index
+// first on ties) go through the wave's LDS slots into a register bitonic sort.
+template <int R>
 __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(const int32_t* __restrict__ cand, int64_t M, int Kr,
                                                                 const void* __restrict__ Q, int q_dt,
                                                                 const void* __restrict__ X, int x_dt, int D,
@@ -31,70 +77,104 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(const int32_t* _
                                                                 const float* __restrict__ x_rnorm, int K,
                                                                 float* __restrict__ out_val,
                                                                 int32_t* __restrict__ out_idx) {
-  __shared__ unsigned long long keys[kRerankMaxKr];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int kp = 1;
-  while (kp < Kr) kp <<= 1;
-  for (int64_t i = blockIdx.x; i < M; i += gridDim.x) {
-    float q[4];
+  __shared__ unsigned long long slots[kRerankThreads / 64][64 * R];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane >> 4, gl = lane & 15;
+  const int E = x_dt == DT_F32 ? 4 : 8;  // elements per 16-byte piece
+  const int per_pass = 16 * E;
+  const int passes = (D + per_pass - 1) / per_pass;  // <= 4 for D <= 256
+  // whole 16-byte pieces when every row starts 16-byte aligned
+  const bool vec = (reinterpret_cast<uintptr_t>(X) & 15) == 0 && (D % E) == 0;
+  unsigned long long* key_slot = slots[wave];
+  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < M; i += (int64_t)gridDim.x * 4) {
+    // this lane's query elements, in the order its pieces cover the depth
+    float q[4][8];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int d = lane + 64 * s;
-      q[s] = d < D ? load_elem(Q, q_dt, i * D + d) : 0.f;
-    }
+    for (int ps = 0; ps < 4; ++ps)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int d = ps * per_pass + gl * E + e;
+        q[ps][e] = (ps < passes && e < E && d < D) ? load_elem(Q, q_dt, i * D + d) : 0.f;
+      }
     float rq = 1.f;
     if (metric == MET_COSINE) {
       float qq = 0.f;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) qq = fmaf(q[s], q[s], qq);
+      for (int d = lane; d < D; d += 64) {
+        const float v = load_elem(Q, q_dt, i * D + d);
+        qq = fmaf(v, v, qq);
+      }
       qq = wave_sum(qq);
       rq = qq > 0.f ? 1.f / sqrtf(qq) : 0.f;
     }
-    for (int c = wave; c < kp; c += 4) {
-      unsigned long long key = 0ull;
-      if (c < Kr) {
-        const int j = cand[i * Kr + c];
+    for (int c0 = 0; c0 < 64 * R; c0 += 4) {
+      const int c = c0 + grp;
+      unsigned long long key = 0ull;  // below every real key: pads sort last
+      if (c0 < Kr) {
+        const int j = c < Kr ? cand[i * Kr + c] : -1;
         float dot = 0.f;
         if (j >= 0) {
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int d = lane + 64 * s;
-            if (d < D) dot = fmaf(q[s], load_elem(X, x_dt, (int64_t)j * D + d), dot);
+          for (int ps = 0; ps < 4; ++ps) {
+            if (ps >= passes) break;
+            const int d0 = ps * per_pass + gl * E;
+            if (d0 < D) {
+              if (x_dt == DT_F32) {
+                const float* xr = reinterpret_cast<const float*>(X) + (int64_t)j * D + d0;
+                if (vec) {
+                  const float4 v = *reinterpret_cast<const float4*>(xr);
+                  dot = fmaf(q[ps][0], v.x, dot);
+                  dot = fmaf(q[ps][1], v.y, dot);
+                  dot = fmaf(q[ps][2], v.z, dot);
+                  dot = fmaf(q[ps][3], v.w, dot);
+                } else {
+                  for (int e = 0; e < 4 && d0 + e < D; ++e) dot = fmaf(q[ps][e], xr[e], dot);
+                }
+              } else {
+                const unsigned short* xr = reinterpret_cast<const unsigned short*>(X) + (int64_t)j * D + d0;
+                if (vec) {
+                  const u32x4 v = *reinterpret_cast<const u32x4*>(xr);
+#pragma unroll
+                  for (int w = 0; w < 4; ++w) {
+                    dot = fmaf(q[ps][2 * w], __uint_as_float(v[w] << 16), dot);
+                    dot = fmaf(q[ps][2 * w + 1], __uint_as_float(v[w] & 0xFFFF0000u), dot);
+                  }
+                } else {
+                  for (int e = 0; e < 8 && d0 + e < D; ++e) dot = fmaf(q[ps][e], __uint_as_float((unsigned)xr[e] << 16), dot);
+                }
+              }
+            }
           }
         }
-        dot = wave_sum(dot);
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 16);
         float sc = dot;
         if (metric == MET_L2) sc = dot - (j >= 0 ? x_half_norm[j] : 0.f);
         if (metric == MET_COSINE) sc = dot * rq * (j >= 0 ? x_rnorm[j] : 0.f);
         if (j < 0) sc = -INFINITY;
-        key = ((unsigned long long)float_key(sc) << 32) | (unsigned)~(unsigned)j;
+        key = c < Kr ? (((unsigned long long)float_key(sc) << 32) | (unsigned)~(unsigned)j) : 0ull;
       }
-      if (lane == 0) keys[c] = key;
+      if (gl == 0) key_slot[c] = key;
     }
-    __syncthreads();
-    for (int size = 2; size <= kp; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int a = tid; a < kp; a += kRerankThreads) {
-          const int b = a ^ stride;
-          if (b > a) {
-            const bool desc = (a & size) == 0;
-            unsigned long long x = keys[a], y = keys[b];
-            if (desc ? (x < y) : (x > y)) {
-              keys[a] = y;
-              keys[b] = x;
-            }
-          }
-        }
-        __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    unsigned long long k[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) k[r] = key_slot[64 * r + lane];
+    wave_sort_desc<R>(k, lane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int e = 64 * r + lane;
+      if (e < K) {
+        const float v = key_float((unsigned)(k[r] >> 32));
+        out_val[i * K + e] = metric == MET_L2 ? -v : v;
+        out_idx[i * K + e] = (int32_t)~(unsigned)(k[r] & 0xFFFFFFFFull);
       }
     }
-    for (int k = tid; k < K; k += kRerankThreads) {
-      const unsigned long long key = keys[k];
-      const float v = key_float((unsigned)(key >> 32));
-      out_val[i * K + k] = metric == MET_L2 ? -v : v;
-      out_idx[i * K + k] = (int32_t)~(unsigned)(key & 0xFFFFFFFFull);
-    }
-    __syncthreads();
+    // the next query rewrites this wave's slots: finish the reads first
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -212,9 +292,22 @@ hipError_t launch_rerank(const int32_t* cand, int64_t M, int Kr, const void* Q, 
   (void)hipGetLastError();  // report only this call's launch errors
   if (M == 0) return hipSuccess;
   if (Kr > kRerankMaxKr || K > Kr || D > 256) return hipErrorInvalidValue;
-  const int64_t grid = M < 65536 ? M : 65536;
-  rerank_kernel<<<(unsigned)grid, kRerankThreads, 0, s>>>(cand, M, Kr, Q, q_dt, X, x_dt, D, metric, x_half_norm,
-                                                          x_rnorm, K, out_val, out_idx);
+  const int64_t want = ceil_div(M, 4);
+  const unsigned grid = (unsigned)(want < 16384 ? want : 16384);
+#define KNN_RERANK(R_)                                                                                             \
+  rerank_kernel<R_><<<grid, kRerankThreads, 0, s>>>(cand, M, Kr, Q, q_dt, X, x_dt, D, metric, x_half_norm, x_rnorm, \
+                                                    K, out_val, out_idx)
+  if (Kr <= 64)
+    KNN_RERANK(1);
+  else if (Kr <= 128)
+    KNN_RERANK(2);
+  else if (Kr <= 256)
+    KNN_RERANK(4);
+  else if (Kr <= 512)
+    KNN_RERANK(8);
+  else
+    KNN_RERANK(16);
+#undef KNN_RERANK
   return hipGetLastError();
 }
 

@@ -3,10 +3,10 @@
 // The distance kernel tracks, per lane, the best of each group of 4 accumulators
 // (4 consecutive database rows) instead of the best single accumulator; that
 // halves the per-score instruction count of the bin update.  A winner recorded
-// as a group is resolved here: one wave recomputes the group's 4 scores from the
-// same prepared (converted) rows and query the matrix unit used, in FP32 with a
-// fixed order (16 lanes per row, each a 16-byte piece, then a butterfly), and
-// keeps the best row, the lower row on ties.  The result can differ from the
+// as a group is resolved here: a group of 16 lanes recomputes the group's 4 scores
+// from the same prepared (converted) rows and query the matrix unit used, in FP32
+// with a fixed order (each lane a strided set of 16-byte pieces, then a butterfly
+// across the 16 lanes), and keeps the best row, the lower row on ties.  The result can differ from the
 // matrix unit's choice only when two rows of the group score within rounding of
 // each other.
 #include "knn_common.cuh"
@@ -15,85 +15,105 @@ namespace knn {
 
 namespace {
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// dot product of two 16-byte pieces (4 FP32, 8 BF16 or 16 FP8 elements), FP32 FMAs
+// in element order.  FP8-e4m3 codes are widened with the hardware conversion
+// (exact: every e4m3 value is an FP32 value).
 template <int DT>
-__device__ __forceinline__ float piece_dot(const u32x4& a, const u32x4& b) {
-  float s = 0.f;
+__device__ __forceinline__ float piece_dot(const u32x4& a, const u32x4& b, float s) {
   if constexpr (DT == DT_F32) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) s = fmaf(__uint_as_float(a[k]), __uint_as_float(b[k]), s);
   } else if constexpr (DT == DT_BF16) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const unsigned wa = a[k >> 1] >> (16 * (k & 1)), wb = b[k >> 1] >> (16 * (k & 1));
-      s = fmaf(__uint_as_float((wa & 0xFFFFu) << 16), __uint_as_float((wb & 0xFFFFu) << 16), s);
+    for (int k = 0; k < 4; ++k) {
+      s = fmaf(__uint_as_float(a[k] << 16), __uint_as_float(b[k] << 16), s);
+      s = fmaf(__uint_as_float(a[k] & 0xFFFF0000u), __uint_as_float(b[k] & 0xFFFF0000u), s);
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const unsigned ca = (a[k >> 2] >> (8 * (k & 3))) & 0xFFu, cb = (b[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-      s = fmaf(fp8_e4m3_value(ca), fp8_e4m3_value(cb), s);
+    for (int k = 0; k < 4; ++k) {
+      const f32x2 a0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a[k], false), a1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a[k], true);
+      const f32x2 b0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)b[k], false), b1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)b[k], true);
+      s = fmaf(a0[0], b0[0], s);
+      s = fmaf(a0[1], b0[1], s);
+      s = fmaf(a1[0], b1[0], s);
+      s = fmaf(a1[1], b1[1], s);
     }
   }
   return s;
 }
 
-// resolve one code in place; the calling wave is uniform on (q_tile, qrow, code)
+// Resolve one code in place with a group of 16 lanes (gl = lane within the group,
+// all 16 lanes pass the same p).  Lane gl takes pieces gl, gl+16, ... of the four
+// rows and of the query row; the four partial sums are reduced across the group
+// with a fixed butterfly, so every lane ends with all four scores.  The best row
+// wins, the lower row on ties.
 template <int DT>
-__device__ __forceinline__ void resolve_one(int32_t* p, const unsigned char* __restrict__ q_tiles, int64_t qrow,
-                                            const unsigned char* __restrict__ db_tiles, int ng) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void resolve16(int32_t* p, const unsigned char* __restrict__ q_tiles, int64_t qrow,
+                                          const unsigned char* __restrict__ db_tiles, int ng, int gl) {
   const int32_t code = *p;
-  if (code > -2) return;
+  if (code > -2) return;  // already a row (or no winner)
   const int64_t start = (int64_t)(-2 - code) * 4;
-  const int r = lane >> 4, pl = lane & 15;
-  const int64_t row = start + r;
   const int64_t TB = tile_bytes(ng);
-  const unsigned char* dtile = db_tiles + (row >> 5) * TB;
+  const unsigned char* dtile = db_tiles + (start >> 5) * TB;
   const unsigned char* qtile = q_tiles + (qrow >> 5) * TB;
-  const int rr = (int)(row & 31), qq = (int)(qrow & 31);
-  float dot = 0.f;
-  for (int pc = pl; pc < 2 * ng; pc += 16) {
+  const int r0 = (int)(start & 31), qq = (int)(qrow & 31);
+  float dot[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int pc = gl; pc < 2 * ng; pc += 16) {
     const int g = pc >> 1, hf = pc & 1;
-    const u32x4 a = *reinterpret_cast<const u32x4*>(dtile + g * 1024 + (rr + 32 * hf) * 16);
     const u32x4 b = *reinterpret_cast<const u32x4*>(qtile + g * 1024 + (qq + 32 * hf) * 16);
-    dot += piece_dot<DT>(a, b);
+    const unsigned char* a = dtile + g * 1024 + (r0 + 32 * hf) * 16;
+    u32x4 ar[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ar[r] = *reinterpret_cast<const u32x4*>(a + r * 16);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dot[r] = piece_dot<DT>(ar[r], b, dot[r]);
   }
 #pragma unroll
-  for (int off = 8; off > 0; off >>= 1) dot += __shfl_xor(dot, off);
-  if constexpr (DT == DT_FP8) {
-    const int ea = (int)dtile[ng * 1024 + 128 + rr] - 127, eb = (int)qtile[ng * 1024 + 128 + qq] - 127;
-    dot = dot * exp2i(ea) * exp2i(eb);
-  }
+  for (int off = 8; off > 0; off >>= 1)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dot[r] += __shfl_xor(dot[r], off, 16);
   const float* init = reinterpret_cast<const float*>(dtile + ng * 1024);
-  float v = init[((rr >> 2) & 1) * 16 + 4 * (rr >> 3) + (rr & 3)] + dot;
-  int best = r;
+  float bv = -INFINITY;
+  int best = 0;
 #pragma unroll
-  for (int off = 16; off < 64; off <<= 1) {
-    const float ov = __shfl_xor(v, off);
-    const int ob = __shfl_xor(best, off);
-    const bool take = (ov > v) || (ov == v && ob < best);
-    v = take ? ov : v;
-    best = take ? ob : best;
+  for (int r = 0; r < 4; ++r) {
+    const int rr = r0 + r;
+    float d = dot[r];
+    if constexpr (DT == DT_FP8) {
+      const int ea = (int)dtile[ng * 1024 + 128 + rr] - 127, eb = (int)qtile[ng * 1024 + 128 + qq] - 127;
+      d = d * exp2i(ea) * exp2i(eb);
+    }
+    const float v = init[((rr >> 2) & 1) * 16 + 4 * (rr >> 3) + (rr & 3)] + d;
+    if (r == 0 || v > bv) {  // strict: the lower row keeps ties
+      bv = v;
+      best = r;
+    }
   }
-  if (lane == 0) *p = (int32_t)(start + best);
+  if (gl == 0) *p = (int32_t)(start + best);
 }
 
 template <int DT>
 __global__ __launch_bounds__(256) void resolve_kernel(int32_t* __restrict__ codes, int64_t rows, int64_t cols,
                                                       int64_t ld, const unsigned char* __restrict__ q_tiles,
                                                       const unsigned char* __restrict__ db_tiles, int ng) {
-  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (e >= rows * cols) return;
-  const int64_t i = e / cols, c = e % cols;
-  resolve_one<DT>(codes + i * ld + c, q_tiles, i, db_tiles, ng);
+  const int gl = threadIdx.x & 15;
+  const int64_t n = rows * cols;
+  const int64_t groups = (int64_t)gridDim.x * 16;
+  for (int64_t e = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4); e < n; e += groups) {
+    const int64_t i = e / cols, c = e - i * cols;
+    resolve16<DT>(codes + i * ld + c, q_tiles, i, db_tiles, ng, gl);
+  }
 }
 
 template <int DT>
 __global__ __launch_bounds__(256) void resolve_rows_kernel(const SelRow* __restrict__ rows_desc, int64_t rows) {
-  const int wave = threadIdx.x >> 6;
+  const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15;
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
     const SelRow d = rows_desc[r];
-    for (int k = wave; k < d.K; k += 4) resolve_one<DT>(d.out_idx + k, d.q_tiles, d.q_row, d.db_tiles, d.ng);
+    for (int k = grp; k < d.K; k += 16) resolve16<DT>(d.out_idx + k, d.q_tiles, d.q_row, d.db_tiles, d.ng, gl);
   }
 }
 
@@ -104,7 +124,9 @@ hipError_t launch_resolve(int dt, int32_t* codes, int64_t rows, int64_t cols, in
   (void)hipGetLastError();  // report only this call's launch errors
   const int64_t n = rows * cols;
   if (n == 0) return hipSuccess;
-  const unsigned grid = (unsigned)ceil_div(n, 4);
+  // 16 codes per workgroup per pass; enough workgroups to fill the chip, then a grid-stride loop
+  const int64_t want = ceil_div(n, 16);
+  const unsigned grid = (unsigned)(want < 8192 ? want : 8192);
   if (dt == DT_F32)
     resolve_kernel<DT_F32><<<grid, 256, 0, s>>>(codes, rows, cols, ld, q_tiles, db_tiles, ng);
   else if (dt == DT_BF16)

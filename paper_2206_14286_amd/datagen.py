@@ -36,6 +36,19 @@ def normal(n: int, d: int, seed: int, scale: float = 1.0) -> np.ndarray:
     return out
 
 
+def normal_device(n: int, d: int, seed: int, scale: float = 1.0, dtype=None, device: str = "cuda"):
+    """i.i.d. N(0, scale^2) rows drawn on the device with torch's seeded generator: for
+    inputs of many GB (the batched and backward workloads) that are timed, not checked
+    element by element against the oracle."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.randn((n, d), generator=g, device=device, dtype=torch.float32)
+    if scale != 1.0:
+        out.mul_(scale)
+    return out if dtype is None else out.to(dtype)
+
+
 def int_mixture(n: int, d: int, seed: int, centres: int = 256, sigma: float = 20.0,
                 centre_seed: int = 12345) -> np.ndarray:
     """Integer-valued rows in [0, 255]: clip(round(mu_c + sigma * eps)), c uniform.
@@ -80,7 +93,11 @@ def targets(m: int, k: int, seed: int) -> np.ndarray:
     return _rng(seed).integers(0, k, size=m).astype(np.int64)
 
 
-# The five workloads: (metric, M, N, D, K, L, description)
+# Databases of the batched workload: (N, D), BF16 N(0, 1) rows, MIPS, K = 10
+BATCHED_DBS = [(100_000, 64), (1_000_000, 96), (4_000_000, 128), (16_000_000, 256)]
+BATCHED_COUNT = 256
+
+# The single-database workloads: (metric, M, N, D, K, L, description)
 WORKLOADS = {
     "mips_small": dict(metric="mips", M=64, N=65536, D=128, K=10, L=2048,
                        data="iid N(0,1) fp32"),

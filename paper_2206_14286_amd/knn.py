@@ -275,8 +275,10 @@ class BatchedPlan:
 
 # ------------------------------------------------------------------------------ backward
 def backward(g: torch.Tensor, idx: torch.Tensor, Q: torch.Tensor, X: torch.Tensor, metric="mips",
-             need_dX: bool = True):
-    """``knn_backward``: (dQ, dX) FP32 for the retrieved-score gradient g (selection fixed)."""
+             need_dX: bool = True, out=None):
+    """``knn_backward``: (dQ, dX) FP32 for the retrieved-score gradient g (selection fixed).
+    ``out=(dQ, dX)``: caller buffers; dQ is overwritten and dX accumulated into (as the C
+    function does), so a fresh gradient needs a zeroed dX."""
     for t, n in ((g, "g"), (idx, "idx"), (Q, "Q"), (X, "X")):
         _dev(t, n)
     if g.dtype != torch.float32 or idx.dtype != torch.int32:
@@ -285,8 +287,11 @@ def backward(g: torch.Tensor, idx: torch.Tensor, Q: torch.Tensor, X: torch.Tenso
         raise TypeError("Q and X must share a dtype")
     M, K = g.shape
     N, D = X.shape
-    dQ = torch.empty((M, D), dtype=torch.float32, device=Q.device)
-    dX = torch.zeros((N, D), dtype=torch.float32, device=Q.device) if need_dX else None
+    if out is not None:
+        dQ, dX = out
+    else:
+        dQ = torch.empty((M, D), dtype=torch.float32, device=Q.device)
+        dX = torch.zeros((N, D), dtype=torch.float32, device=Q.device) if need_dX else None
     _check(lib().knn_backward(_ptr(g), _ptr(idx), _ptr(Q), _ptr(X), _in_dtype(Q), M, N, D, K, _metric(metric),
                               _ptr(dQ), _ptr(dX), _stream()))
     return dQ, dX
