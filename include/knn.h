@@ -3,10 +3,10 @@
  *
  * The library implements the two-kernel search of "TPU-KNN: K Nearest
  * Neighbor Search at Peak FLOP/s" (Chern et al., 2022):
- *   PartialReduce (Sec. 4, Algorithm 1): the query-database distance GEMM fused
+ *   PartialReduce (Sec. 5, Algorithm 1): the query-database distance GEMM fused
  *     with a reduction that keeps, for each query, the best score and its row
  *     index in each of L bins, so the M x N score matrix never reaches memory;
- *   ExactRescoring (Sec. 4): the exact top-K over the M x L bin winners.
+ *   ExactRescoring (Sec. 5): the exact top-K over the M x L bin winners.
  * Scores (Sec. 2 and the appendix on Euclidean search):
  *   KNN_MIPS    <q, x>                      maximised (eq. 2)
  *   KNN_L2      |x|^2 / 2 - <q, x>          minimised (eq. l2final); returned as is,
@@ -17,7 +17,7 @@
  *   [floor(b N / L), floor((b + 1) N / L)),
  * which is Algorithm 1's ShiftRight(j, W) when N = L * 2^W.  Inside a bin the
  * lowest row index wins ties; results are ordered best first, ties by lower index.
- * Expected recall (Sec. 4.1, eq. recall) is at least ((L-1)/L)^(K-1).
+ * Expected recall (Sec. 5.1, eq. recall) is at least ((L-1)/L)^(K-1).
  *
  * Conventions for every entry point:
  *   - Pointers named Q, X, out_*, bins_*, g, idx, dQ, dX are DEVICE pointers,
@@ -63,11 +63,11 @@ typedef struct knn_plan knn_plan; /* a batched search plan (opaque) */
 
 /* ------------------------------------------------------------------ helpers (host only) */
 
-/* Smallest L with ((L-1)/L)^(K-1) >= r (Sec. 4.1, eq. l:approx, exact inverse),
+/* Smallest L with ((L-1)/L)^(K-1) >= r (Sec. 5.1, eq. l:approx, exact inverse),
  * clamped to [K, N]; K == 1 gives 1.  Returns -1 for K < 1, N < 1 or r outside (0, 1). */
 int64_t knn_bins_for_recall(int32_t K, double recall_target, int64_t N);
 
-/* ((L-1)/L)^(K-1) (Sec. 4.1, eq. recall); NaN for K < 1 or L < 1. */
+/* ((L-1)/L)^(K-1) (Sec. 5.1, eq. recall); NaN for K < 1 or L < 1. */
 double knn_expected_recall_bound(int32_t K, int64_t L);
 
 /* First row of bin b: floor(b N / L).  -1 for invalid arguments. */
@@ -139,7 +139,7 @@ knn_status knn_db_search(const knn_db* db, const void* Q, int32_t q_dtype, int64
  * knn_query_prepare: queries -> the layout the distance kernel reads (same conversion as
  *   the database: cosine normalisation, compute type, padding).  qbuf is a device buffer
  *   of at least knn_query_buffer_bytes(db, M) bytes, owned by the caller.
- * knn_partial_reduce: PartialReduce alone (Sec. 4, Algorithm 1): the M x L bin winners
+ * knn_partial_reduce: PartialReduce alone (Sec. 5, Algorithm 1): the M x L bin winners
  *   (bins_val FP32, bins_idx int32, device, row-major), compute-type scores in the
  *   metric's own sign; no top-K (the `aggregate_to_topk = False` form of the paper's op).
  *   bins_idx is in compact form: an entry >= 0 is the winning row; an entry e <= -2

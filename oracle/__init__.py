@@ -8,7 +8,7 @@ Parts:
   * ``knn_oracle.c`` (FP64, OpenMP over queries): scores, Algorithm 1
     (PartialReduce) on contiguous balanced bins, exact top-K of the bin
     winners, exact K-NN by full sort, dense reference gradients.
-  * this module: the ctypes wrapper for it, the recall model of Sec. 4.1
+  * this module: the ctypes wrapper for it, the recall model of Sec. 5.1
     (eq. recall, eq. l:approx and the appendix on the number of bins), the
     exact recall expectation for fixed balanced bins, recall metrics
     (eq. recall-def) and the reference quantisers (BF16 round-to-nearest-even,
@@ -184,7 +184,7 @@ def backward(g, a, Q, X, metric):
 
 
 # ----------------------------------------------------------------------------------------
-# recall model (Sec. 4.1 and the appendix on the number of bins)
+# recall model (Sec. 5.1 and the appendix on the number of bins)
 # ----------------------------------------------------------------------------------------
 def recall_bound_paper(K: int, L: int) -> float:
     """eq. recall: E[Z]/K = ((L-1)/L)^(K-1), Z = balls alone in their bin."""

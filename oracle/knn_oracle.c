@@ -13,7 +13,7 @@
  *   - the bin-wise partial reduction of Algorithm 1 (PartialReduce): in each
  *     of L bins keep the best score and its index, scanning rows in increasing
  *     order and replacing only on a strictly better score;
- *   - the exact top-K over the bin winners (the ExactRescoring step, Sec. 4);
+ *   - the exact top-K over the bin winners (the ExactRescoring step, Sec. 5);
  *   - the exact K-NN ground truth (eq. 1 / eq. 2) by a full sort of all N scores.
  *
  * Readings of the paper taken here (the paper leaves these open):

@@ -1,29 +1,35 @@
 // knn_fused.hip -- the distance GEMM fused with the bin-wise partial reduction
-// (PartialReduce, Sec. 4, Algorithm 1), for gfx950.
+// (PartialReduce, Sec. 5, Algorithm 1), for gfx950.
 //
 // Work item = (query block, bin chunk).  A workgroup of 4 waves owns 4*32*NCB
 // queries and a chunk of whole, consecutive bins (rows [r0, r1)), so every bin is
 // finished inside one workgroup and the M x N scores never leave the chip
-// (the paper's point about aggregating inside the kernel, Sec. 3.2, eq. blas3).
+// (the paper's point about aggregating inside the kernel, Sec. 4.2, eq. blas3).
 //
 //   * Each wave keeps the B operand fragments of its 32*NCB queries in registers
 //     for the whole item (the paper's query-block reuse, Algorithm 2's ib loop).
 //   * The database streams through LDS in 32-row tiles (Algorithm 2's jb loop):
-//     the whole workgroup copies tile t+1 with direct global->LDS loads while it
-//     computes tile t, so each tile is read from L2/HBM once per workgroup.
+//     the workgroup copies tiles S ahead with direct buffer->LDS loads while it
+//     computes, so each tile is read from L2/HBM once per workgroup.
 //   * Scores come from 32x32 MFMA instructions (FP32 32x32x2, BF16 32x32x16,
 //     FP8 32x32x64 with a per-row power-of-two scale) with FP32 accumulation.
 //     In the 32x32 output layout lane l holds 16 rows of one query column
 //     (rows 8*(i/4) + 4*(l/32) + i%4 of the tile, query l%32), so the bin update is
-//     per-lane register work: one compare and two conditional moves per score,
-//     the 3 COPs of Algorithm 1, against a running (best value, row) pair.
+//     per-lane register work.  Algorithm 1 spends a compare and two conditional
+//     moves per score; here the running best is updated per group of 4 rows (one
+//     max3/max, a compare and two conditional moves per 4 scores), the group's row
+//     being found afterwards (knn_resolve.hip), and these instructions are
+//     interleaved with the next tile's matrix instructions.
 //   * L2 starts the accumulators from -|x|^2/2 (see knn_prepare.hip), so every
 //     metric is a maximisation of the accumulator.
-//   * Tiles that straddle a bin boundary or the chunk edge take a slower path:
-//     the wave spills the tile's scores to its private LDS scratch and one lane
-//     per query walks the 32 rows in order, closing bins as it crosses them.
+//   * A tile with one bin boundary inside updates the bins on either side with
+//     masked group updates (exact rows for the one group the boundary splits);
+//     tiles at the item's edges or with several boundaries walk their rows in
+//     order, exchanging scores between the two lane halves.
+//   * Finished bins are staged per wave in LDS and written 16 bins at a time as
+//     64-byte row segments.
 //   * Bins: contiguous balanced row ranges; ties inside a bin go to the lowest row
-//     (strict compare in increasing row order, then lowest index when the two
+//     (strict compare in increasing row order, then lowest unit when the two
 //     lane halves are merged).
 //   * Workgroup ids are mapped so that the workgroups running on one XCD at a
 //     time share the same bin chunk, and its tiles are served from that XCD's L2.
@@ -35,7 +41,13 @@ namespace knn {
 
 namespace {
 
-constexpr int kSlowFloats = 2 * 32 * 33;  // per-wave scratch: 2 column blocks x 32 queries x 33
+// Bins leave the kernel through a per-wave LDS window of kWin consecutive bins x 64
+// queries (values and codes), written out as 64-byte row segments once the window
+// is complete instead of one 4-byte store per query and bin.  Rows of the window
+// are padded to kWinStride words so the per-query writes fall in distinct banks.
+constexpr int kWin = 16;
+constexpr int kWinStride = kWin + 1;
+constexpr int kStageWords = 2 * 64 * kWinStride;  // per wave: values, then codes
 
 template <int NG>
 struct TileGeom {
@@ -50,7 +62,7 @@ struct TileGeom {
 
 template <int NG>
 constexpr int lds_bytes() {
-  return TileGeom<NG>::kStages * TileGeom<NG>::kLdsBytes + kWaves * kSlowFloats * 4;
+  return TileGeom<NG>::kStages * TileGeom<NG>::kLdsBytes + kWaves * kStageWords * 4;
 }
 
 // wait until at most N vector-memory loads of this wave are outstanding
@@ -258,12 +270,81 @@ __device__ __forceinline__ void merge_halves(float v, unsigned u, float& mv, uns
 
 // bins output: value in the metric's sign; row >= 0, or -2 - start/4 for a 4-row group
 // starting at row `start`, or -1 when the bin saw no finite score
-__device__ __forceinline__ void write_bin(float* __restrict__ outV, int32_t* __restrict__ outA, int64_t ldo,
-                                          int64_t q, int64_t bin, float v, unsigned u, float sign) {
-  outV[q * ldo + bin] = sign * v;
-  int32_t code = -1;
-  if (u != kNoUnit) code = (u & 1u) ? -2 - (int32_t)(u >> 3) : (int32_t)(u >> 1);
-  outA[q * ldo + bin] = code;
+__device__ __forceinline__ int32_t bin_code(unsigned u) {
+  if (u == kNoUnit) return -1;
+  return (u & 1u) ? -2 - (int32_t)(u >> 3) : (int32_t)(u >> 1);
+}
+
+// put one query's finished bin into the wave's output window
+__device__ __forceinline__ void stage_bin(float* st, int qlocal, int bin, float v, unsigned u, float sign) {
+  st[qlocal * kWinStride + (bin & (kWin - 1))] = sign * v;
+  reinterpret_cast<int32_t*>(st)[64 * kWinStride + qlocal * kWinStride + (bin & (kWin - 1))] = bin_code(u);
+}
+
+// Write the window of bins [wb, wb + kWin) clipped to the item's bins [b0, b1) for the
+// wave's queries.  A full window goes out as 16-byte stores, four lanes per query
+// row (64 contiguous bytes each); a clipped one (item edges) bin by bin.
+template <int NCB>
+__device__ __forceinline__ void drain_window(const float* st, int wb, int b0, int b1, float* __restrict__ outV,
+                                             int32_t* __restrict__ outA, int64_t ldo, int64_t wq0, int64_t M,
+                                             bool vec_ok, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int32_t* sa = reinterpret_cast<const int32_t*>(st) + 64 * kWinStride;
+  if (vec_ok && wb >= b0 && wb + kWin <= b1) {
+#pragma unroll
+    for (int s = 0; s < NCB * 32 / 16; ++s) {
+      const int ql = 16 * s + (lane >> 2), part = lane & 3;
+      const int64_t q = wq0 + ql;
+      const float* sv = st + ql * kWinStride + 4 * part;
+      const int32_t* si = sa + ql * kWinStride + 4 * part;
+      const float4 v = make_float4(sv[0], sv[1], sv[2], sv[3]);
+      const int4 a = make_int4(si[0], si[1], si[2], si[3]);
+      if (q < M) {
+        *reinterpret_cast<float4*>(outV + q * ldo + wb + 4 * part) = v;
+        *reinterpret_cast<int4*>(outA + q * ldo + wb + 4 * part) = a;
+      }
+    }
+  } else {
+    const int lo = wb > b0 ? wb : b0, hi = (wb + kWin) < b1 ? (wb + kWin) : b1;
+    const int64_t q = wq0 + lane;
+    if (lane < NCB * 32 && q < M) {
+      for (int b = lo; b < hi; ++b) {
+        outV[q * ldo + b] = st[lane * kWinStride + (b & (kWin - 1))];
+        outA[q * ldo + b] = sa[lane * kWinStride + (b & (kWin - 1))];
+      }
+    }
+  }
+  // the window's slots are rewritten by the next bins only after these reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Walks the first rows floor(b N / L) of consecutive bins without dividing:
+// `next` is the first row of the bin after the current one, rem = (b+1) N mod L.
+struct BinCursor {
+  int64_t next;
+  unsigned rem, nr, L;  // rem, N mod L, L (all < 2^31)
+  int64_t nq;           // N / L
+  __device__ __forceinline__ int64_t peek2() const { return next + nq + (rem + nr >= L ? 1 : 0); }
+  __device__ __forceinline__ void advance() {
+    const unsigned r = rem + nr;
+    const bool c = r >= L;
+    next += nq + (c ? 1 : 0);
+    rem = c ? r - L : r;
+  }
+};
+
+__device__ __forceinline__ BinCursor make_cursor(int64_t b, int64_t N, int64_t L) {
+  BinCursor c;
+  c.next = bin_start(b + 1, N, L);
+  c.rem = (unsigned)(((b + 1) * N) % L);
+  c.nr = (unsigned)(N % L);
+  c.L = (unsigned)L;
+  c.nq = N / L;
+  return c;
 }
 
 template <int DT, int NG, int NCB>
@@ -278,7 +359,9 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int h = lane >> 5, ql = lane & 31;
-  float* scratch = reinterpret_cast<float*>(lds + S * G::kLdsBytes) + wave * kSlowFloats;
+  float* stage = reinterpret_cast<float*>(lds + S * G::kLdsBytes) + wave * kStageWords;
+  const bool vec_ok = ((reinterpret_cast<uintptr_t>(outV) | reinterpret_cast<uintptr_t>(outA)) & 15) == 0 &&
+                      (ldo & 3) == 0;
   const TileLoadPlan<NG> plan = make_load_plan<NG>(wave, lane);
 
   // rows and tiles fit in 32 bits (N < 2^31)
@@ -308,7 +391,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     bu[cb] = kNoUnit;
   }
   int cur_bin = (int)b0;
-  int next_start = (int)bin_start(b0 + 1, N, L);
+  BinCursor cursor = make_cursor(b0, N, L);
 
   // Software pipeline over the chunk's tiles.  Step t: the tile loads run S tiles
   // ahead (direct global->LDS); the fragments of tile t+1 are read from LDS and
@@ -364,7 +447,8 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     for (int cb = 0; cb < NCB; ++cb) asm volatile("" : "+v"(nbv[cb]), "+v"(nbu[cb]));
     const int lo = t0 > r0 ? t0 : r0;
     const int hi = (t0 + 32) < r1 ? (t0 + 32) : r1;
-    const bool fast = lo == t0 && hi == t0 + 32 && t0 + 32 <= next_start;  // whole tile in the current bin
+    const bool whole = lo == t0 && hi == t0 + 32;  // the tile lies inside the item's rows
+    const bool fast = whole && t0 + 32 <= cursor.next;  // whole tile in the current bin
     float obv[NCB];
     unsigned obu[NCB];
 #pragma unroll
@@ -374,93 +458,138 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       bv[cb] = fast ? nbv[cb] : bv[cb];
       bu[cb] = fast ? nbu[cb] : bu[cb];
     }
-    if (fast) {
-      if (t0 + 32 == next_start) {  // the bin ends with this tile
+    auto flush_all = [&]() {  // the current bin is complete: stage it, open the next
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          float mv;
-          unsigned mu;
-          merge_halves(bv[cb], bu[cb], mv, mu);
-          const int64_t q = wq0 + cb * 32 + ql;
-          if (h == 0 && q < M) write_bin(outV, outA, ldo, q, cur_bin, mv, mu, sign);
-          bv[cb] = -INFINITY;
-          bu[cb] = kNoUnit;
-        }
-        ++cur_bin;
-        next_start = (int)bin_start(cur_bin + 1, N, L);
-      }
-      return;
-    }
-    // tile crosses a bin boundary or the chunk edge: walk its rows in order
-    int cb2 = cur_bin, ns = next_start;
-#pragma unroll
-    for (int rd = 0; rd < (NCB + 1) / 2; ++rd) {
-      const int cA = 2 * rd, cB = 2 * rd + 1;
-      const bool hasB = cB < NCB;
-      float sv = -INFINITY;
-      unsigned su = kNoUnit;
-      {
+      for (int cb = 0; cb < NCB; ++cb) {
         float mv;
         unsigned mu;
-        merge_halves(obv[cA], obu[cA], mv, mu);
-        if (h == 0) { sv = mv; su = mu; }
-        if (hasB) {
-          merge_halves(obv[cB], obu[cB], mv, mu);
-          if (h == 1) { sv = mv; su = mu; }
-        }
+        merge_halves(bv[cb], bu[cb], mv, mu);
+        if (h == (cb & 1)) stage_bin(stage, cb * 32 + ql, cur_bin, mv, mu, sign);
+        bv[cb] = -INFINITY;
+        bu[cb] = kNoUnit;
       }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int row = 8 * (i >> 2) + 4 * h + (i & 3);
-        scratch[ql * 33 + row] = acc_c[cA][i];
-        if (hasB) scratch[32 * 33 + ql * 33 + row] = acc_c[cB][i];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const bool lane_on = (h == 0) || hasB;
-      const int64_t q = wq0 + (cA + h) * 32 + ql;
-      cb2 = cur_bin;
-      ns = next_start;
-      const float* my = scratch + h * 32 * 33 + ql * 33;
-      for (int jj = 0; jj < 32; ++jj) {
-        const int j = t0 + jj;
-        if (j < lo || j >= hi) continue;
-        if (j == ns) {
-          if (lane_on && q < M) write_bin(outV, outA, ldo, q, cb2, sv, su, sign);
-          sv = -INFINITY;
-          su = kNoUnit;
-          ++cb2;
-          ns = (int)bin_start(cb2 + 1, N, L);
-        }
-        const float s = my[jj];
-        if (s > sv) { sv = s; su = 2u * (unsigned)j; }
-      }
-      if (hi == ns) {
-        if (lane_on && q < M) write_bin(outV, outA, ldo, q, cb2, sv, su, sign);
-        sv = -INFINITY;
-        su = kNoUnit;
-        ++cb2;
-        ns = cb2 < b1 ? (int)bin_start(cb2 + 1, N, L) : r1;
-      }
-      // back to the per-half form: half 0 carries the open bin's state
-      {
-        const float vA = __shfl(sv, ql);
-        const unsigned uA = __shfl(su, ql);
-        bv[cA] = h == 0 ? vA : -INFINITY;
-        bu[cA] = h == 0 ? uA : kNoUnit;
-        if (hasB) {
-          const float vB = __shfl(sv, 32 + ql);
-          const unsigned uB = __shfl(su, 32 + ql);
-          bv[cB] = h == 0 ? vB : -INFINITY;
-          bu[cB] = h == 0 ? uB : kNoUnit;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      if ((cur_bin & (kWin - 1)) == kWin - 1 || cur_bin == b1 - 1)
+        drain_window<NCB>(stage, cur_bin & ~(kWin - 1), (int)b0, (int)b1, outV, outA, ldo, wq0, M, vec_ok, lane);
+      ++cur_bin;
+      cursor.advance();
+    };
+    if (fast) {
+      if (t0 + 32 == cursor.next) flush_all();  // the bin ends with this tile
+      return;
     }
-    cur_bin = cb2;
-    next_start = ns;
+    if (whole && cursor.peek2() >= t0 + 32) {
+      // One bin boundary inside the tile, at row p (the bins on either side hold at
+      // least the rest of the tile).  Groups of 4 rows that lie on one side update that
+      // side's bin as group units; only the group containing p (k* = p/8, when p is
+      // not a multiple of 4) is split, and it is folded in row by row with exact rows.
+      const int p = (int)(cursor.next - t0);  // 1..31, uniform
+      const int kstar = (p & 3) ? (p >> 3) : -1;
+      const unsigned gbase = 2u * (unsigned)t0 + 8u * (unsigned)h;  // 2 * (first row of group 0)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        float cv = obv[cb], nv = -INFINITY;
+        unsigned cu = obu[cb], nu = kNoUnit;
+        static_for<0, 4>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          const int gr = 8 * k + 4 * h;  // tile row of the lane's group k
+          if (k == kstar) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const float a = acc_c[cb][4 * k + j];
+              const bool in_cur = gr + j < p;
+              const unsigned code = gbase + 16u * k + 2u * j;
+              const float ac = in_cur ? a : -INFINITY, an = in_cur ? -INFINITY : a;
+              const bool c1 = ac > cv, c2 = an > nv;
+              cv = c1 ? ac : cv;
+              cu = c1 ? code : cu;
+              nv = c2 ? an : nv;
+              nu = c2 ? code : nu;
+            }
+          } else {
+            const float g = fmaxf(fmaxf(fmaxf(acc_c[cb][4 * k], acc_c[cb][4 * k + 1]), acc_c[cb][4 * k + 2]),
+                                  acc_c[cb][4 * k + 3]);
+            const bool in_cur = gr < p;  // the whole group is on one side
+            const unsigned code = gbase + 16u * k + 1u;
+            const float gc = in_cur ? g : -INFINITY, gn = in_cur ? -INFINITY : g;
+            const bool c1 = gc > cv, c2 = gn > nv;
+            cv = c1 ? gc : cv;
+            cu = c1 ? code : cu;
+            nv = c2 ? gn : nv;
+            nu = c2 ? code : nu;
+          }
+        });
+        bv[cb] = cv;
+        bu[cb] = cu;
+        obv[cb] = nv;
+        obu[cb] = nu;
+      }
+      flush_all();
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        bv[cb] = obv[cb];
+        bu[cb] = obu[cb];
+      }
+      if (t0 + 32 == cursor.next) flush_all();  // the next bin ends with the tile too
+      return;
+    }
+    // The tile crosses the item's edge or holds several bin boundaries: walk its rows
+    // in order.  Lane (h, ql) follows query ql of column block h (block 0 when NCB is
+    // 1); a row's score is read from the lane half that holds it, with one exchange
+    // between the halves per row.
+    static_assert(NCB <= 2, "the row walk pairs at most two column blocks");
+    constexpr int cB = NCB - 1;
+    float sv;
+    unsigned su;
+    {
+      float mv;
+      unsigned mu;
+      merge_halves(obv[0], obu[0], mv, mu);
+      sv = mv;
+      su = mu;
+      if (NCB == 2) {
+        merge_halves(obv[cB], obu[cB], mv, mu);
+        if (h == 1) {
+          sv = mv;
+          su = mu;
+        }
+      }
+    }
+    const bool lane_on = h == 0 || NCB == 2;
+    auto flush_row = [&]() {
+      if (lane_on) stage_bin(stage, h * 32 + ql, cur_bin, sv, su, sign);
+      if ((cur_bin & (kWin - 1)) == kWin - 1 || cur_bin == b1 - 1)
+        drain_window<NCB>(stage, cur_bin & ~(kWin - 1), (int)b0, (int)b1, outV, outA, ldo, wq0, M, vec_ok, lane);
+      sv = -INFINITY;
+      su = kNoUnit;
+      ++cur_bin;
+      cursor.advance();
+    };
+    for (int jj = lo - t0; jj < hi - t0; ++jj) {  // uniform bounds
+      const int j = t0 + jj;
+      if (j == cursor.next) flush_row();
+      const int ir = 4 * (jj >> 3) + (jj & 3), hr = (jj >> 2) & 1;  // accumulator and lane half of row jj
+      const float a = acc_c[0][ir], b = acc_c[cB][ir];
+      const float other = __shfl_xor(h == 0 ? b : a, 32);
+      const float x = hr == h ? (h == 0 ? a : b) : other;
+      if (x > sv) {
+        sv = x;
+        su = 2u * (unsigned)j;
+      }
+    }
+    if (hi == cursor.next) flush_row();
+    // back to the per-half form: half 0 carries the open bin's state
+    {
+      const float vA = __shfl(sv, ql);
+      const unsigned uA = __shfl(su, ql);
+      bv[0] = h == 0 ? vA : -INFINITY;
+      bu[0] = h == 0 ? uA : kNoUnit;
+      if (NCB == 2) {
+        const float vB = __shfl(sv, 32 + ql);
+        const unsigned uB = __shfl(su, 32 + ql);
+        bv[cB] = h == 0 ? vB : -INFINITY;
+        bu[cB] = h == 0 ? uB : kNoUnit;
+      }
+    }
   };
   for (int t = t_first; t <= t_last; t += 2) {
     step(t, acc_a, acc_b);
@@ -469,8 +598,16 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   }
 }
 
+// Occupancy: the short FP8 tiles have the least matrix work per tile to hide the bin
+// update behind, so their kernels are held to 3 waves per SIMD (<= 168 VGPRs).
+template <int DT, int NG>
+constexpr int min_waves() {
+  return (DT == DT_FP8 && NG <= 4) ? 3 : 1;
+}
+
 template <int DT, int NG, int NCB>
-__global__ __launch_bounds__(256) void fused_kernel(FusedParams p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<DT, NG>(), 8)))
+void fused_kernel(FusedParams p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const int bid = blockIdx.x;
   const int xcd = bid & 7, slot = bid >> 3;

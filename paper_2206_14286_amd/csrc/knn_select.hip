@@ -1,4 +1,4 @@
-// knn_select.hip -- exact top-K over candidate lists (the ExactRescoring step, Sec. 4).
+// knn_select.hip -- exact top-K over candidate lists (the ExactRescoring step, Sec. 5).
 //
 // The paper sorts the M x L bin winners with a bitonic sort and truncates to K
 // (O(M L log^2 L)).  Here each row gets one workgroup running an MSB-first radix

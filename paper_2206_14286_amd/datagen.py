@@ -4,7 +4,7 @@ This module only draws random numbers; it holds none of the search's arithmetic.
 Both the HIP path's tests/benchmark and the CPU oracle take their inputs from here.
 
 Stand-ins (no dataset is available or reproduced):
-  * SIFT1M-shaped (Sec. 5 / Table 2, Euclidean): integer entries in [0, 255] drawn
+  * SIFT1M-shaped (App. A.5, Table 2, Euclidean): integer entries in [0, 255] drawn
     from a Gaussian mixture of ``centres`` centres (centres uniform integers in
     [0, 255]^D, sigma 20, rounded and clipped);
   * GloVe-1.2M-shaped (Table 2, cosine, D = 100 padded to 128 by the search):
@@ -12,7 +12,7 @@ Stand-ins (no dataset is available or reproduced):
     unit-normalised;
   * plain i.i.d. standard normal (MIPS).
 Rows are emitted in draw order, never sorted by cluster: the recall model of
-Sec. 4.1 assumes the positions of the true neighbours are uniformly random.
+Sec. 5.1 assumes the positions of the true neighbours are uniformly random.
 
 Seeds: numpy PCG64; stream ``seed`` for the database, ``seed + 1`` for the
 queries, ``seed + 2`` for targets and batch sizes.

@@ -59,6 +59,9 @@ CASES = [
     ("cosine", 100, 3333, 100, 20, 300, "fp8"),
     ("mips", 64, 2500, 128, 10, 50, "fp8"),
     ("l2", 129, 1500, 64, 5, 1500, "fp8"),
+    ("l2", 200, 3000, 64, 10, 80, "bf16"),         # bins of 37-38 rows: one boundary per tile
+    ("mips", 100, 2000, 128, 5, 45, "fp8"),        # bins of 44-45 rows
+    ("cosine", 64, 4100, 128, 10, 120, "fp32"),    # bins of 34-35 rows, ragged tail tile
 ]
 
 

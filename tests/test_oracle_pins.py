@@ -174,7 +174,7 @@ def test_nested_bins_recall_monotone():
     assert np.all(prev == 1.0)
 
 
-# ---------------------------------------------------------------- recall model (Sec. 4.1)
+# ---------------------------------------------------------------- recall model (Sec. 5.1)
 def _enumerated_recall(N, L, K):
     """Exact E[recall] by running the oracle on every placement of the K true neighbours."""
     tot = Fraction(0)
@@ -199,7 +199,7 @@ def _enumerated_recall(N, L, K):
     (11, 4, 2, None),
 ])
 def test_recall_expectation_by_enumeration(N, L, K, expect):
-    """Sec. 4.1: recall = (#bins holding a true neighbour)/K.  The closed form
+    """Sec. 5.1: recall = (#bins holding a true neighbour)/K.  The closed form
     (1/K) sum_b [1 - C(N-B_b,K)/C(N,K)] equals exhaustive enumeration of all placements
     through the oracle's own search, and is >= the paper's bound ((L-1)/L)^(K-1)."""
     enum = _enumerated_recall(N, L, K)
