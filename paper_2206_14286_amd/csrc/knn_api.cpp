@@ -236,7 +236,7 @@ extern "C" knn_status knn_db_export(const knn_db* db, void* codes, int32_t* expo
     const int rr = (int)(r & 31);
     for (int d = 0; d < db->D; ++d) {
       const int g = d / (2 * E), hf = (d % (2 * E)) / E, k = d % E;
-      memcpy(out + ((size_t)r * db->D + d) * es, tb + g * 1024 + (rr + 32 * hf) * 16 + k * es, es);
+      memcpy(out + ((size_t)r * db->D + d) * es, tb + piece_offset(rr, g, hf, db->ng) + k * es, es);
     }
     const unsigned char* aux = tb + db->ng * 1024;
     if (exponents) exponents[r] = (int32_t)aux[128 + rr] - 127;

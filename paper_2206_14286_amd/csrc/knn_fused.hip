@@ -92,14 +92,25 @@ struct TileLoadPlan {
   unsigned aux_off;
 };
 
+// LDS copy of a tile: the global piece layout (knn_internal.h: each group of 4 rows
+// contiguous) with the 64-byte sub-blocks of row group rg permuted by XOR with
+// (rg % 4) * 64.  Each 16-lane quarter of a copy instruction then reads one aligned
+// 256-byte global chunk, and each quarter of a fragment read (16 rows of one
+// half, 4 row groups) hits four different 64-byte bank ranges.
+template <int NG>
+__device__ __forceinline__ int lds_swizzle(int off) {
+  return off ^ (((off / (NG * 128)) & 3) << 6);  // an involution: also maps LDS -> global
+}
+
 template <int NG>
 __device__ __forceinline__ TileLoadPlan<NG> make_load_plan(int wave, int lane) {
   using G = TileGeom<NG>;
   TileLoadPlan<NG> p;
 #pragma unroll
   for (int it = 0; it < G::kPerWave; ++it) {
-    const int k = it * 64 * kWaves + wave * 64 + lane;
-    p.frag_off[it] = (unsigned)(k < G::kMain ? k : G::kMain - 1) * 16u;
+    int k = it * 64 * kWaves + wave * 64 + lane;  // 16-byte LDS slot written by this lane
+    k = k < G::kMain ? k : G::kMain - 1;          // pad slots re-read the last piece
+    p.frag_off[it] = (unsigned)lds_swizzle<NG>(k * 16);
   }
   p.aux_off = (unsigned)(NG * 1024 + (wave * 4 + (lane & 3)) * 16);
   return p;
@@ -151,8 +162,14 @@ __device__ __forceinline__ void read_tile(TileRegs<NG>& r, const unsigned char* 
 #pragma unroll
   for (int i = 0; i < 16; ++i) r.init[i] = auxf[h * 16 + i];
   r.sa = tile[G::kMainBytes + 128 + (lane & 31)];
+  // piece (row q, group g, half h) of the swizzled copy: the XOR flips bit 6 (half)
+  // and bit 7 (group parity) of the offset inside the row group's block
+  const int q = lane & 31, rg = q >> 2, sw = (rg & 3) << 6;
+  const int base = rg * NG * 128 + (q & 3) * 16 + ((h << 6) ^ (sw & 64));
+  const int a_even = base + (sw & 128), a_odd = base - (sw & 128);  // (g ^ b7) * 128 = g * 128 +- b7 * 128
 #pragma unroll
-  for (int g = 0; g < NG; ++g) r.af[g] = *reinterpret_cast<const u32x4*>(tile + g * 1024 + lane * 16);
+  for (int g = 0; g < NG; ++g)
+    r.af[g] = *reinterpret_cast<const u32x4*>(tile + ((g & 1) ? a_odd : a_even) + g * 128);
 }
 
 // acc[cb] = init + sum over the tile depth of A(tile rows) x B(query columns)
@@ -377,7 +394,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   for (int cb = 0; cb < NCB; ++cb) {
     const unsigned char* qt = q_tiles + ((wq0 >> 5) + cb) * TB;
 #pragma unroll
-    for (int g = 0; g < NG; ++g) bq[cb][g] = *reinterpret_cast<const u32x4*>(qt + g * 1024 + lane * 16);
+    for (int g = 0; g < NG; ++g) bq[cb][g] = *reinterpret_cast<const u32x4*>(qt + piece_offset(ql, g, h, NG));
     sb[cb] = qt[NG * 1024 + 128 + ql];
   }
   const bool active = wq0 < M;
@@ -485,18 +502,20 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       const int p = (int)(cursor.next - t0);  // 1..31, uniform
       const int kstar = (p & 3) ? (p >> 3) : -1;
       const unsigned gbase = 2u * (unsigned)t0 + 8u * (unsigned)h;  // 2 * (first row of group 0)
+      const int h4 = 4 * h;
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         float cv = obv[cb], nv = -INFINITY;
         unsigned cu = obu[cb], nu = kNoUnit;
         static_for<0, 4>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          const int gr = 8 * k + 4 * h;  // tile row of the lane's group k
+          // the lane's group k holds tile rows 8k + 4h + j; row < p  <=>  4h < p - 8k - j
+          // (the right side is uniform: a compare against a scalar)
           if (k == kstar) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const float a = acc_c[cb][4 * k + j];
-              const bool in_cur = gr + j < p;
+              const bool in_cur = h4 < p - 8 * k - j;
               const unsigned code = gbase + 16u * k + 2u * j;
               const float ac = in_cur ? a : -INFINITY, an = in_cur ? -INFINITY : a;
               const bool c1 = ac > cv, c2 = an > nv;
@@ -508,7 +527,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
           } else {
             const float g = fmaxf(fmaxf(fmaxf(acc_c[cb][4 * k], acc_c[cb][4 * k + 1]), acc_c[cb][4 * k + 2]),
                                   acc_c[cb][4 * k + 3]);
-            const bool in_cur = gr < p;  // the whole group is on one side
+            const bool in_cur = h4 < p - 8 * k;  // the whole group is on one side
             const unsigned code = gbase + 16u * k + 1u;
             const float gc = in_cur ? g : -INFINITY, gn = in_cur ? -INFINITY : g;
             const bool c1 = gc > cv, c2 = gn > nv;
@@ -644,9 +663,11 @@ __device__ __forceinline__ void run_group_item(const GroupDesc& gd, const WorkIt
                         it.b1, gd.out_sign, gd.binV, gd.binA, gd.ldo, lds);
 }
 
+// Held to 2 waves per SIMD (<= 256 VGPRs): with every depth's case inlined the
+// compiler would otherwise size the registers for all of them at once.
 template <int DT>
-__global__ __launch_bounds__(256) void fused_persistent_kernel(const GroupDesc* __restrict__ groups,
-                                                               const WorkItem* __restrict__ items, int64_t n_items) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void fused_persistent_kernel(
+    const GroupDesc* __restrict__ groups, const WorkItem* __restrict__ items, int64_t n_items) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   for (int64_t w = blockIdx.x; w < n_items; w += gridDim.x) {
     const WorkItem it = items[w];

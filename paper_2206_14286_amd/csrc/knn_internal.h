@@ -1,15 +1,16 @@
 // knn_internal.h -- declarations shared by the host API and the HIP kernels.
 //
 // Prepared-row layout (databases and queries alike).  Rows are grouped in tiles
-// of 32.  A tile holds NG "fragment groups" of 1 KiB followed by a 256-byte aux
-// block:
-//   group g, lane l (0..63), 16 bytes: row (l % 32) of the tile, dimensions
-//     g*2E + (l/32)*E + [0, E), E = 16 bytes / element size
-//     (FP32: 4, BF16: 8, FP8: 16 elements),
-//   so one 64-lane 16-byte load of a group is exactly one MFMA A (or B) operand
-//   fragment of the 32x32 matrix instructions (two consecutive groups for the
-//   FP8 32x32x64 step), and every load of the distance kernel reads 1 KiB of
-//   contiguous memory.
+// of 32.  A tile holds NG*1 KiB of row data followed by a 256-byte aux block.
+// The row data is cut into 16-byte pieces: piece (r, g, hf) holds dimensions
+//   g*2E + hf*E + [0, E) of tile row r, E = 16 bytes / element size
+//   (FP32: 4, BF16: 8, FP8: 16 elements), g < NG, hf < 2,
+// and is stored at byte piece_offset(r, g, hf) = (r/4)*NG*128 + g*128 + hf*64 + (r%4)*16:
+// each group of 4 consecutive rows is one contiguous block of NG*128 bytes (what
+// the resolve step reads for a 4-row winner).  The distance kernel copies a tile to
+// LDS so that LDS piece [g][l] (l = 0..63) is piece (l % 32, g, l / 32): one 64-lane
+// 16-byte LDS load of group g is then exactly one MFMA A (or B) operand fragment of
+// the 32x32 matrix instructions (two consecutive groups for the FP8 32x32x64 step).
 //   aux bytes [0,128):   float init[2][16]; init[h][i] = -|x~_r|^2/2 (L2, else 0) for
 //                        row r = 8*(i/4) + 4*h + i%4, the row that accumulator i of a
 //                        lane in half h holds in the 32x32 MFMA output layout;
@@ -37,6 +38,10 @@ __host__ __device__ inline int dpad_for(int D, int dt) {
 }
 __host__ __device__ inline int groups_for(int dpad, int dt) { return dpad * elem_bytes(dt) / 32; }
 __host__ __device__ inline int64_t tile_bytes(int ng) { return (int64_t)ng * 1024 + kAuxBytes; }
+// byte offset of piece (row r of the tile, group g, half hf) inside a tile
+__host__ __device__ inline int piece_offset(int r, int g, int hf, int ng) {
+  return (r >> 2) * ng * 128 + g * 128 + hf * 64 + (r & 3) * 16;
+}
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // first row of bin b (contiguous balanced bins)

@@ -1,12 +1,13 @@
 // knn_prepare.hip -- row preparation for the distance kernel.
 //
-// One thread per row.  For cosine the row is unit-normalised in FP32 (|x|^2
+// One thread per row (64-thread workgroups, loads batched 16 at a time so the
+// row is streamed rather than fetched element by element).  For cosine the row is unit-normalised in FP32 (|x|^2
 // summed in dimension order with one rounding per product and per sum, correctly
 // rounded square root and divisions), which makes cosine search an inner-product
 // search (Sec. 2: MIPS equals cosine search on l2-normalised data).  The row is
 // then converted to the compute type, zero-padded to the MFMA depth (the paper
 // pads GloVe's D = 100 to 128, appendix "Benchmark details") and scattered into
-// the fragment layout described in knn_internal.h.  For L2 the aux block gets
+// the piece layout described in knn_internal.h.  For L2 the aux block gets
 // -|x~|^2/2 of the converted row: the distance kernel starts its accumulators
 // from it, so <q,x> - |x|^2/2 (the negated relaxed distance of eq. l2final)
 // comes out of the matrix unit with no extra per-score instruction.
@@ -42,9 +43,12 @@ __device__ void prepare_row(const void* src, int in_dt, int64_t r, int64_t rows,
   const int64_t base = r * (int64_t)D;
   float ss = 0.f;
   if (valid)
-    for (int d = 0; d < D; ++d) {
-      float x = load_elem(src, in_dt, base + d);
-      ss = ss + x * x;
+    for (int d0 = 0; d0 < D; d0 += 16) {  // 16 loads in flight, summed in dimension order
+      float x[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = d0 + k < D ? load_elem(src, in_dt, base + d0 + k) : 0.f;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) ss = ss + x[k] * x[k];
     }
   const float nrm = sqrtf(ss);  // correctly rounded square root (HIP default)
   if (valid && orig_half_norm) orig_half_norm[r] = 0.5f * ss;
@@ -54,7 +58,13 @@ __device__ void prepare_row(const void* src, int in_dt, int64_t r, int64_t rows,
   int e = 0;
   if (CDT == DT_FP8) {
     float amax = 0.f;
-    for (int d = 0; d < D; ++d) amax = fmaxf(amax, fabsf(v.get(d)));
+    for (int d0 = 0; d0 < D; d0 += 16) {
+      float x[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = v.get(d0 + k);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) amax = fmaxf(amax, fabsf(x[k]));
+    }
     e = fp8_row_exponent(amax);
   }
   const float down = exp2i(-e), up = exp2i(e);
@@ -88,7 +98,7 @@ __device__ void prepare_row(const void* src, int in_dt, int64_t r, int64_t rows,
         }
         hh = hh + deq * deq;
       }
-      *reinterpret_cast<u32x4*>(tb + g * 1024 + (rr + 32 * hf) * 16) = w;
+      *reinterpret_cast<u32x4*>(tb + piece_offset(rr, g, hf, ng)) = w;
     }
   }
   unsigned char* aux = tb + ng * 1024;
@@ -98,7 +108,7 @@ __device__ void prepare_row(const void* src, int in_dt, int64_t r, int64_t rows,
 }
 
 template <int CDT>
-__global__ __launch_bounds__(256) void prepare_kernel(const void* src, int in_dt, int64_t rows, int D, int ng,
+__global__ __launch_bounds__(64) void prepare_kernel(const void* src, int in_dt, int64_t rows, int D, int ng,
                                                       int metric, int database, unsigned char* tiles,
                                                       int64_t n_rows_padded, float* orig_half_norm,
                                                       float* orig_rnorm) {
@@ -108,7 +118,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void* src, int in_dt
 }
 
 template <int CDT>
-__global__ __launch_bounds__(256) void prepare_segments_kernel(const QSeg* segs, int nseg, int64_t total_rows,
+__global__ __launch_bounds__(64) void prepare_segments_kernel(const QSeg* segs, int nseg, int64_t total_rows,
                                                                int in_dt) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= total_rows) return;
@@ -132,15 +142,15 @@ hipError_t launch_prepare(const void* src, int in_dt, int64_t rows, int D, int m
   const int ng = groups_for(dpad_for(D, compute), compute);
   const int64_t n = n_tiles * kTileRows;
   if (n == 0) return hipSuccess;
-  const unsigned grid = (unsigned)ceil_div(n, 256);
+  const unsigned grid = (unsigned)ceil_div(n, 64);
   if (compute == DT_F32)
-    prepare_kernel<DT_F32><<<grid, 256, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+    prepare_kernel<DT_F32><<<grid, 64, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
                                                 orig_half_norm, orig_rnorm);
   else if (compute == DT_BF16)
-    prepare_kernel<DT_BF16><<<grid, 256, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+    prepare_kernel<DT_BF16><<<grid, 64, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
                                                  orig_half_norm, orig_rnorm);
   else
-    prepare_kernel<DT_FP8><<<grid, 256, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+    prepare_kernel<DT_FP8><<<grid, 64, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
                                                 orig_half_norm, orig_rnorm);
   return hipGetLastError();
 }
@@ -149,13 +159,13 @@ hipError_t launch_prepare_segments(const QSeg* d_segs, int nseg, int64_t total_r
                                    hipStream_t s) {
   (void)hipGetLastError();  // report only this call's launch errors
   if (total_rows == 0 || nseg == 0) return hipSuccess;
-  const unsigned grid = (unsigned)ceil_div(total_rows, 256);
+  const unsigned grid = (unsigned)ceil_div(total_rows, 64);
   if (compute == DT_F32)
-    prepare_segments_kernel<DT_F32><<<grid, 256, 0, s>>>(d_segs, nseg, total_rows, in_dt);
+    prepare_segments_kernel<DT_F32><<<grid, 64, 0, s>>>(d_segs, nseg, total_rows, in_dt);
   else if (compute == DT_BF16)
-    prepare_segments_kernel<DT_BF16><<<grid, 256, 0, s>>>(d_segs, nseg, total_rows, in_dt);
+    prepare_segments_kernel<DT_BF16><<<grid, 64, 0, s>>>(d_segs, nseg, total_rows, in_dt);
   else
-    prepare_segments_kernel<DT_FP8><<<grid, 256, 0, s>>>(d_segs, nseg, total_rows, in_dt);
+    prepare_segments_kernel<DT_FP8><<<grid, 64, 0, s>>>(d_segs, nseg, total_rows, in_dt);
   return hipGetLastError();
 }
 

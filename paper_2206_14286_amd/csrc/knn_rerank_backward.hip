@@ -24,47 +24,6 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
-  const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, m), hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), m);
-  return ((unsigned long long)hi << 32) | lo;
-}
-
-// Sort 64*R keys held by one wave (element e = 64*r + lane) in descending order:
-// a bitonic network whose exchanges within a lane's registers are plain compares
-// and whose exchanges across lanes are shuffles.
-template <int R>
-__device__ __forceinline__ void wave_sort_desc(unsigned long long (&k)[R], int lane) {
-  constexpr int N = 64 * R;
-#pragma unroll
-  for (int size = 2; size <= N; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      if (stride >= 64) {
-        const int rs = stride >> 6;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if (r & rs) continue;  // handle each in-lane pair once, from its lower element
-          const int e = 64 * r + lane;
-          const bool desc = (e & size) == 0;
-          const unsigned long long a = k[r], b = k[r | rs];
-          const bool sw = desc ? (a < b) : (a > b);
-          k[r] = sw ? b : a;
-          k[r | rs] = sw ? a : b;
-        }
-      } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int e = 64 * r + lane;
-          const bool desc = (e & size) == 0, lower = (e & stride) == 0;
-          const unsigned long long o = shfl_xor_u64(k[r], stride);
-          const bool take_max = desc == lower;
-          k[r] = take_max ? (o > k[r] ? o : k[r]) : (o < k[r] ? o : k[r]);
-        }
-      }
-    }
-  }
-}
-
 // One wave per query.  Candidate scores: groups of 16 lanes each take a candidate
 // row and split its depth into 16-byte pieces (4 FP32 or 8 BF16 elements per lane
 // per pass); a fixed 16-lane butterfly sums the pieces.  Keys (score, lower index

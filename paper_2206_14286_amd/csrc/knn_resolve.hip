@@ -63,8 +63,8 @@ __device__ __forceinline__ void resolve16(int32_t* p, const unsigned char* __res
   float dot[4] = {0.f, 0.f, 0.f, 0.f};
   for (int pc = gl; pc < 2 * ng; pc += 16) {
     const int g = pc >> 1, hf = pc & 1;
-    const u32x4 b = *reinterpret_cast<const u32x4*>(qtile + g * 1024 + (qq + 32 * hf) * 16);
-    const unsigned char* a = dtile + g * 1024 + (r0 + 32 * hf) * 16;
+    const u32x4 b = *reinterpret_cast<const u32x4*>(qtile + piece_offset(qq, g, hf, ng));
+    const unsigned char* a = dtile + piece_offset(r0, g, hf, ng);  // the 4 rows' pieces are adjacent
     u32x4 ar[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) ar[r] = *reinterpret_cast<const u32x4*>(a + r * 16);

@@ -7,8 +7,10 @@
 // best score T exactly; if T is shared by more rows than are still needed, a
 // second radix select on the row indices keeps the lowest ones.  The K survivors
 // are then bitonic-sorted in LDS by (score, lower index first) and written best
-// first.  Cost per row: O(L) reads per pass instead of O(L log^2 L).  Candidates
-// may still be 4-row group codes; they keep their code (resolved afterwards).
+// first.  Cost per row: O(L) reads per pass instead of O(L log^2 L).  Rows of at
+// most 1024 candidates instead take one wave each and a register bitonic sort.
+// Candidates may still be 4-row group codes; they keep their code (resolved
+// afterwards).
 #include "knn_common.cuh"
 
 namespace knn {
@@ -187,6 +189,36 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(const SelRow* 
   }
 }
 
+// Rows of at most 64*R candidates: one wave per row, keys (score, then lower unit)
+// held in registers and sorted by a bitonic network of shuffles; no LDS, no
+// workgroup barriers.  Same order as the radix path.
+template <int R>
+__global__ __launch_bounds__(256) void select_wave_kernel(const float* __restrict__ V, const int32_t* __restrict__ A,
+                                                          int64_t rows, int n, int64_t ldv, int K, int minimize,
+                                                          float* __restrict__ out_val, int32_t* __restrict__ out_idx,
+                                                          int64_t ldout) {
+  const int lane = threadIdx.x & 63;
+  const float sgn = minimize ? -1.f : 1.f;
+  if (K > n) K = n;
+  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gridDim.x * 4) {
+    unsigned long long k[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int c = 64 * i + lane;
+      k[i] = c < n ? (((unsigned long long)float_key(sgn * V[r * ldv + c]) << 32) | unit_lo(A[r * ldv + c])) : 0ull;
+    }
+    wave_sort_desc<R>(k, lane);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int e = 64 * i + lane;
+      if (e < K) {
+        out_val[r * ldout + e] = sgn * key_float((unsigned)(k[i] >> 32));
+        out_idx[r * ldout + e] = unit_code((unsigned)(k[i] & 0xFFFFFFFFull));
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t n, int64_t ldv, int K,
@@ -194,6 +226,24 @@ hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t
   (void)hipGetLastError();  // report only this call's launch errors
   if (rows == 0) return hipSuccess;
   if (K > kMaxK || K < 1 || n < 1) return hipErrorInvalidValue;
+  if (n <= 1024) {  // short rows: a wave per row, sorted in registers
+    const int64_t want = ceil_div(rows, 4);
+    const unsigned grid = (unsigned)(want < 65536 ? want : 65536);
+    const int nn = (int)n, mz = minimize ? 1 : 0;
+#define KNN_SELW(R_) select_wave_kernel<R_><<<grid, 256, 0, s>>>(V, A, rows, nn, ldv, K, mz, out_val, out_idx, ldout)
+    if (n <= 64)
+      KNN_SELW(1);
+    else if (n <= 128)
+      KNN_SELW(2);
+    else if (n <= 256)
+      KNN_SELW(4);
+    else if (n <= 512)
+      KNN_SELW(8);
+    else
+      KNN_SELW(16);
+#undef KNN_SELW
+    return hipGetLastError();
+  }
   const int64_t grid = rows < 65536 ? rows : 65536;
   select_kernel<<<(unsigned)grid, kSelThreads, 0, s>>>(V, A, rows, n, ldv, K, minimize ? 1 : 0, out_val, out_idx,
                                                        ldout);
