@@ -218,7 +218,7 @@ __device__ __forceinline__ void mma_tile(f32x16 (&acc)[NCB], const TileRegs<NG>&
 
 // The matrix instructions of one tile, in fixed order (one k-step for every column
 // block, then the next k-step), with the U = 4*NCB units of the previous tile's
-// bin update spread evenly between them.  A full scheduling barrier after each
+// bin update spread evenly between them, two at a time.  A full scheduling barrier after each
 // group pins the order: every unit's VALU instructions issue while the matrix
 // unit is busy with the group just issued, and alternating column blocks keeps
 // consecutive matrix instructions independent.
@@ -262,9 +262,11 @@ __device__ __forceinline__ void mma_tile_interleaved(f32x16 (&acc)[NCB], const T
                                                        s == 0 ? r.init : acc[cb], 0, 0, 0);
       }
     });
-    static_for<0, U>([&](auto uc) {
-      constexpr int u = decltype(uc)::value;
-      if constexpr (u * P / U == s) unit(uc);
+    // units go in pairs, so the two independent updates interleave (no stall between
+    // a compare and the select that reads its lane mask)
+    static_for<0, U / 2>([&](auto pc) {
+      constexpr int pr = decltype(pc)::value;
+      if constexpr (pr * P / (U / 2) == s) unit(pc);
     });
     __builtin_amdgcn_sched_barrier(0);
   });
@@ -274,10 +276,22 @@ __device__ __forceinline__ void mma_tile_interleaved(f32x16 (&acc)[NCB], const T
 // consecutive rows (one lane's accumulators 4k..4k+3) whose exact row is resolved
 // later from the prepared rows.  Units are keyed u = 2*start + is_group (unsigned,
 // 0xFFFFFFFF = none); units of one bin never overlap, so ordering by u orders by row.
+// Inside a lane, a group unit is kept without the lane half's row offset (4 rows
+// for half 1: the same for all of the lane's groups), so the per-tile update can
+// take it from a scalar; merge_halves adds the offset back.
 constexpr unsigned kNoUnit = 0xFFFFFFFFu;
 
+// max of three finite floats in one instruction (the compiler's own max3 matching
+// pairs the operands differently and leaves a third max)
+__device__ __forceinline__ float max3f(float a, float b, float c) {
+  float r;
+  asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 // merge the two lane halves' (value, unit) of one query: larger value, then lower unit
-__device__ __forceinline__ void merge_halves(float v, unsigned u, float& mv, unsigned& mu) {
+__device__ __forceinline__ void merge_halves(float v, unsigned u, int h, float& mv, unsigned& mu) {
+  if (u != kNoUnit && (u & 1u)) u += 8u * (unsigned)h;  // group unit: true first row
   const float ov = __shfl_xor(v, 32);
   const unsigned ou = __shfl_xor(u, 32);
   const bool take = (ov > v) || (ov == v && ou < u);
@@ -437,7 +451,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     if (t + S <= t_last) load_tile<NG>(db_tiles + (int64_t)(t + S) * TB, buf(t), plan, wave, lane);
     if (!active) return;
     const int t0 = t << 5;
-    const unsigned ubase = 2u * (unsigned)t0 + 8u * (unsigned)h + 1u;  // unit of accumulator group 0
+    const unsigned gu0 = 2u * (unsigned)t0 + 1u;  // lane-local unit of accumulator group 0 (uniform)
     float nbv[NCB];
     unsigned nbu[NCB];
 #pragma unroll
@@ -449,14 +463,29 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     __builtin_amdgcn_sched_barrier(0);
     // unit u: accumulator group k = u / NCB (rows t0 + 8k + 4h + 0..3) of column block
     // cb = u % NCB of tile t, against the running best (groups in row order)
-    mma_tile_interleaved<DT, NG, NCB>(acc_n, fr, bq, sb, [&](auto uc) {
-      constexpr int u = decltype(uc)::value;
-      constexpr int k = u / NCB, cb = u % NCB;
-      const float gk = fmaxf(fmaxf(fmaxf(acc_c[cb][4 * k], acc_c[cb][4 * k + 1]), acc_c[cb][4 * k + 2]),
-                             acc_c[cb][4 * k + 3]);
-      const bool c = gk > nbv[cb];
-      nbv[cb] = c ? gk : nbv[cb];
-      nbu[cb] = c ? ubase + 16u * k : nbu[cb];
+    mma_tile_interleaved<DT, NG, NCB>(acc_n, fr, bq, sb, [&](auto pc) {
+      constexpr int pr = decltype(pc)::value;
+      constexpr int uA = 2 * pr, uB = 2 * pr + 1;
+      constexpr int kA = uA / NCB, cA = uA % NCB, kB = uB / NCB, cB = uB % NCB;
+      // two max3 fold a group into the running best; it changed iff the group won
+      const float mA = max3f(acc_c[cA][4 * kA], acc_c[cA][4 * kA + 1], acc_c[cA][4 * kA + 2]);
+      const float mB = max3f(acc_c[cB][4 * kB], acc_c[cB][4 * kB + 1], acc_c[cB][4 * kB + 2]);
+      if constexpr (cA != cB) {  // two column blocks: independent states
+        const float nA = max3f(mA, acc_c[cA][4 * kA + 3], nbv[cA]);
+        const float nB = max3f(mB, acc_c[cB][4 * kB + 3], nbv[cB]);
+        const bool wA = nA > nbv[cA], wB = nB > nbv[cB];
+        nbu[cA] = wA ? gu0 + 16u * kA : nbu[cA];
+        nbu[cB] = wB ? gu0 + 16u * kB : nbu[cB];
+        nbv[cA] = nA;
+        nbv[cB] = nB;
+      } else {  // one column block: groups kA < kB update the same state in order
+        const float nA = max3f(mA, acc_c[cA][4 * kA + 3], nbv[cA]);
+        const float nB = max3f(mB, acc_c[cB][4 * kB + 3], nA);
+        const bool wA = nA > nbv[cA], wB = nB > nA;
+        nbu[cA] = wA ? gu0 + 16u * kA : nbu[cA];
+        nbu[cA] = wB ? gu0 + 16u * kB : nbu[cA];
+        nbv[cA] = nB;
+      }
     });
     // materialise the update here, inside the region with the MFMAs, rather than
     // letting the compiler sink it into the (rarely not taken) fast branch below
@@ -480,7 +509,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       for (int cb = 0; cb < NCB; ++cb) {
         float mv;
         unsigned mu;
-        merge_halves(bv[cb], bu[cb], mv, mu);
+        merge_halves(bv[cb], bu[cb], h, mv, mu);
         if (h == (cb & 1)) stage_bin(stage, cb * 32 + ql, cur_bin, mv, mu, sign);
         bv[cb] = -INFINITY;
         bu[cb] = kNoUnit;
@@ -528,7 +557,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
             const float g = fmaxf(fmaxf(fmaxf(acc_c[cb][4 * k], acc_c[cb][4 * k + 1]), acc_c[cb][4 * k + 2]),
                                   acc_c[cb][4 * k + 3]);
             const bool in_cur = h4 < p - 8 * k;  // the whole group is on one side
-            const unsigned code = gbase + 16u * k + 1u;
+            const unsigned code = gu0 + 16u * k;  // lane-local group unit
             const float gc = in_cur ? g : -INFINITY, gn = in_cur ? -INFINITY : g;
             const bool c1 = gc > cv, c2 = gn > nv;
             cv = c1 ? gc : cv;
@@ -562,11 +591,11 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     {
       float mv;
       unsigned mu;
-      merge_halves(obv[0], obu[0], mv, mu);
+      merge_halves(obv[0], obu[0], h, mv, mu);
       sv = mv;
       su = mu;
       if (NCB == 2) {
-        merge_halves(obv[cB], obu[cB], mv, mu);
+        merge_halves(obv[cB], obu[cB], h, mv, mu);
         if (h == 1) {
           sv = mv;
           su = mu;
