@@ -34,6 +34,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Sources that determine the distance kernel's machine code and launch shape: the
+# hardware counter figures under profiles/ are only reported while these are unchanged.
+KERNEL_SOURCES = ["paper_2206_14286_amd/csrc/knn_fused.hip", "paper_2206_14286_amd/csrc/knn_internal.h",
+                  "paper_2206_14286_amd/csrc/knn_common.cuh", "paper_2206_14286_amd/csrc/knn_api.cpp",
+                  "paper_2206_14286_amd/build.py"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "fused_l2_sift_counters.md")
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(compute):
+    """HBM bytes per launch of the distance kernel for `compute`, from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current sources."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    vals = {}
+    for line in open(COUNTERS_FILE):
+        line = line.strip()
+        if line.startswith("- source_sha256:"):
+            vals["sha"] = line.split(":", 1)[1].strip()
+        elif line.startswith(f"- traffic_bytes_per_launch[{compute}]:"):
+            vals["bytes"] = float(line.split(":", 1)[1].strip())
+    if vals.get("sha") != kernel_source_digest() or "bytes" not in vals:
+        return None
+    return vals["bytes"]
+
+
 def dpad(D, compute):
     step = 64 if compute == "fp8" else 32
     return (D + step - 1) // step * step
@@ -323,7 +357,7 @@ def main():
             "peak": PEAK_TFLOPS[args.compute],
             "unit": "TFLOP/s",
             "frac": head["fused_frac_of_peak"],
-            "traffic": None,
+            "traffic": measured_traffic(args.compute),
             "kernel": "fused distance GEMM + bin reduce",
             "kernel_ms": head["fused_kernel_ms"],
             "flops_per_launch": flops,

@@ -176,9 +176,11 @@ typedef struct {
  * nothing and may be captured into a hipGraph.  The batch pointers are bound now:
  * replays read the queries from, and write the results to, the same buffers.
  * For each database the plan picks L >= knn_bins_for_recall(max K, recall_target, N)
- * and the kernel tiling; with tune != 0 it times candidates on `stream` with
- * hipEvents (the autotuner) and caches the choice in the JSON file `cache_path`
- * (NULL: no cache); with tune == 0 it uses a fixed heuristic.
+ * (more bins than that when one bin's rows would not fit the 2 MiB that a group of
+ * workgroups streams through an XCD's L2; more bins never lower the expected
+ * recall) and the kernel tiling; with tune != 0 it times candidates on `stream`
+ * with hipEvents (the autotuner) and caches the choice in the JSON file
+ * `cache_path` (NULL: no cache); with tune == 0 it uses a fixed heuristic.
  * Synchronises `stream`. */
 knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn_batch* batches, int32_t nb,
                            int32_t q_dtype, double recall_target, int32_t tune, const char* cache_path,

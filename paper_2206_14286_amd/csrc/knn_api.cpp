@@ -70,12 +70,34 @@ int pick_ncb(int dt, int ng, int64_t M) {
 }
 
 // bins per work item: enough items to fill the chip, at least ~256 rows per item
-int64_t pick_bins_per_chunk(int64_t N, int64_t L, int64_t n_qb, int64_t target_items = 8192) {
+// The workgroups that share a bin chunk run together on one XCD and stream its
+// tiles through that XCD's 4 MB L2; a chunk of at most this many prepared bytes
+// stays resident while they do (larger chunks let them drift apart and re-read).
+constexpr double kChunkBytes = 2.0 * 1024 * 1024;
+
+double row_bytes(int ng) { return double(tile_bytes(ng)) / kTileRows; }
+
+// bins per work item: about target_items items in all, at least 256 rows, and at
+// most kChunkBytes of prepared rows (unless one bin is larger)
+int64_t pick_bins_per_chunk(int64_t N, int64_t L, int64_t n_qb, int ng, int64_t target_items = 8192) {
   const double bin_rows = double(N) / double(L);
   int64_t want_chunks = std::max<int64_t>(1, ceil_div(target_items, std::max<int64_t>(1, n_qb)));
   int64_t bpc = std::max<int64_t>(1, L / want_chunks);
   int64_t min_bpc = std::max<int64_t>(1, (int64_t)std::ceil(256.0 / bin_rows));
-  return std::min<int64_t>(L, std::max(bpc, min_bpc));
+  int64_t max_bpc = std::max<int64_t>(1, (int64_t)(kChunkBytes / (bin_rows * row_bytes(ng))));
+  bpc = std::max(bpc, min_bpc);
+  bpc = std::min(bpc, std::max(max_bpc, min_bpc));
+  // whole 16-bin output windows of the distance kernel: item edges on window edges
+  if (bpc >= 16) bpc = bpc / 16 * 16;
+  return std::min<int64_t>(L, bpc);
+}
+
+// Smallest L whose bins each fit in one L2-resident chunk (never above N/32: bins
+// keep at least one tile of rows).  Used by batched plans, which may choose more
+// bins than the recall target needs: more bins never lower the expected recall.
+int64_t bins_for_l2(int64_t N, int ng) {
+  const int64_t l = (int64_t)std::ceil(double(N) * row_bytes(ng) / kChunkBytes);
+  return std::max<int64_t>(1, std::min<int64_t>(l, N / kTileRows));
 }
 
 struct DevBuf {  // stream-ordered temporary
@@ -104,7 +126,7 @@ struct knn_db {
 
 struct GroupPlan {
   int32_t db;
-  int64_t M = 0, L = 0, bins_per_chunk = 0, n_qb = 0, n_chunks = 0, q_tiles_n = 0;
+  int64_t M = 0, L = 0, L_min = 0, bins_per_chunk = 0, n_qb = 0, n_chunks = 0, q_tiles_n = 0;
   int32_t ncb = 1, K_max = 1;
   unsigned char* q_tiles = nullptr;
   float* binV = nullptr;
@@ -260,7 +282,7 @@ static knn_status search_core(const knn_db* db, const void* Q, int32_t q_dtype, 
   const int64_t QB = (int64_t)kWaves * 32 * ncb;
   const int64_t n_qb = ceil_div(M, QB);
   const int64_t q_tiles_n = n_qb * QB / kTileRows;
-  const int64_t bpc = pick_bins_per_chunk(db->N, L, n_qb);
+  const int64_t bpc = pick_bins_per_chunk(db->N, L, n_qb, db->ng);
   const int64_t n_chunks = ceil_div(L, bpc);
 
   DevBuf qbuf, vbuf, abuf, cbufv, cbufi;
@@ -398,7 +420,7 @@ extern "C" knn_status knn_partial_reduce(const knn_db* db, const void* qbuf, int
   const int ncb = pick_ncb(db->compute, db->ng, M);
   const int64_t QB = (int64_t)kWaves * 32 * ncb;
   const int64_t n_qb = ceil_div(M, QB);
-  const int64_t bpc = pick_bins_per_chunk(db->N, L, n_qb);
+  const int64_t bpc = pick_bins_per_chunk(db->N, L, n_qb, db->ng);
   FusedParams p{};
   p.db_tiles = db->tiles;
   p.q_tiles = (const unsigned char*)qbuf;
@@ -756,9 +778,11 @@ extern "C" knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn
     p->max_K = std::max(p->max_K, g.K_max);
     const int64_t N = dbs[d]->N;
     g.L = std::max<int64_t>(knn_bins_for_recall(g.K_max, recall_target, N), g.K_max);
+    g.L_min = g.L;
+    g.L = std::min<int64_t>(N, std::max(g.L, bins_for_l2(N, dbs[d]->ng)));
     g.ncb = (g.M > 128 && dbs[d]->ng <= 8) ? 2 : 1;
     const int64_t QB = (int64_t)kWaves * 32 * g.ncb;
-    g.bins_per_chunk = pick_bins_per_chunk(N, g.L, ceil_div(std::max<int64_t>(g.M, 1), QB), 4096);
+    g.bins_per_chunk = pick_bins_per_chunk(N, g.L, ceil_div(std::max<int64_t>(g.M, 1), QB), dbs[d]->ng, 4096);
     p->groups.push_back(g);
   }
   knn_status st = build_plan_buffers(p, s);
@@ -780,14 +804,15 @@ extern "C" knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn
         g.bins_per_chunk = it->second[2];
         continue;
       }
-      // candidates: L in {L_min, 2 L_min, 4 L_min} (never below the recall bound),
-      // ncb in {1, 2}, work-item sizes around the heuristic
+      // candidates: L in {L_min, 2 L_min, 4 L_min, the L2-resident choice} (never
+      // below the recall bound), ncb in {1, 2}, work-item sizes around the heuristic
       const int64_t N = dbs[g.db]->N;
-      const int64_t Lmin = g.L;
+      const int64_t Lmin = g.L_min;
       double best = 1e30;
       GroupPlan bestg = g;
-      for (int64_t lm : {int64_t(1), int64_t(2), int64_t(4)}) {
-        const int64_t Lc = std::min<int64_t>(N, Lmin * lm);
+      const int64_t Lfit = std::max(Lmin, bins_for_l2(N, dbs[g.db]->ng));
+      for (int64_t Lc0 : {Lmin, 2 * Lmin, 4 * Lmin, Lfit}) {
+        const int64_t Lc = std::min<int64_t>(N, Lc0);
         for (int ncb : {1, 2}) {
           if (!fused_supported(compute, dbs[g.db]->ng, ncb)) continue;
           if (ncb == 2 && dbs[g.db]->ng > 8) continue;
@@ -797,7 +822,7 @@ extern "C" knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn
             GroupPlan c = g;
             c.L = Lc;
             c.ncb = ncb;
-            c.bins_per_chunk = pick_bins_per_chunk(N, Lc, nqb, target);
+            c.bins_per_chunk = pick_bins_per_chunk(N, Lc, nqb, dbs[g.db]->ng, target);
             p->groups[gi] = c;
             if (build_plan_buffers(p, s) != KNN_OK) continue;
             double ms = time_group(p, gi, s);
