@@ -780,7 +780,7 @@ extern "C" knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn
     g.L = std::max<int64_t>(knn_bins_for_recall(g.K_max, recall_target, N), g.K_max);
     g.L_min = g.L;
     g.L = std::min<int64_t>(N, std::max(g.L, bins_for_l2(N, dbs[d]->ng)));
-    g.ncb = (g.M > 128 && dbs[d]->ng <= 8) ? 2 : 1;
+    g.ncb = g.M > 128 ? 2 : 1;
     const int64_t QB = (int64_t)kWaves * 32 * g.ncb;
     g.bins_per_chunk = pick_bins_per_chunk(N, g.L, ceil_div(std::max<int64_t>(g.M, 1), QB), dbs[d]->ng, 4096);
     p->groups.push_back(g);
@@ -815,7 +815,6 @@ extern "C" knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn
         const int64_t Lc = std::min<int64_t>(N, Lc0);
         for (int ncb : {1, 2}) {
           if (!fused_supported(compute, dbs[g.db]->ng, ncb)) continue;
-          if (ncb == 2 && dbs[g.db]->ng > 8) continue;
           const int64_t QB = (int64_t)kWaves * 32 * ncb;
           const int64_t nqb = ceil_div(g.M, QB);
           for (int64_t target : {int64_t(1024), int64_t(4096)}) {

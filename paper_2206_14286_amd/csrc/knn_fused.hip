@@ -272,6 +272,74 @@ __device__ __forceinline__ void mma_tile_interleaved(f32x16 (&acc)[NCB], const T
   });
 }
 
+// Depths whose double-buffered form would exceed two waves' registers per SIMD use
+// one accumulator set (FP32 keeps the double-buffered form: its matrix instructions
+// are long enough that one wave per SIMD keeps the unit busy).
+template <int DT, int NG>
+constexpr bool kSingleAcc() {
+  return DT != DT_F32 && NG >= 12;
+}
+
+// acc[cb] = init + the tile's products, with the A fragments read from LDS in chunks
+// of 4 groups, each chunk's reads issued before the previous chunk's matrix
+// instructions (2 x 4 fragment registers instead of NG).
+template <int DT, int NG, int NCB>
+__device__ __forceinline__ void mma_tile_chunked(f32x16 (&acc)[NCB], const unsigned char* tile,
+                                                 const u32x4 (&bq)[NCB][NG], const int (&sb)[NCB]) {
+  using G = TileGeom<NG>;
+  constexpr int CH = 4;
+  static_assert(NG % CH == 0 && DT != DT_F32, "chunked form: BF16 / FP8, NG a multiple of 4");
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const float* auxf = reinterpret_cast<const float*>(tile + G::kMainBytes);
+  f32x16 init;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) init[i] = auxf[h * 16 + i];
+  const int sa = tile[G::kMainBytes + 128 + (lane & 31)];
+  const int q = lane & 31, rg = q >> 2, sw = (rg & 3) << 6;
+  const int base = rg * NG * 128 + (q & 3) * 16 + ((h << 6) ^ (sw & 64));
+  const int a_even = base + (sw & 128), a_odd = base - (sw & 128);
+  u32x4 fa[2][CH];
+  auto read_chunk = [&](u32x4 (&f)[CH], int c) {
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int g = c * CH + j;
+      f[j] = *reinterpret_cast<const u32x4*>(tile + ((g & 1) ? a_odd : a_even) + g * 128);
+    }
+  };
+  read_chunk(fa[0], 0);
+  static_for<0, NG / CH>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    if constexpr (c + 1 < NG / CH) read_chunk(fa[(c + 1) & 1], c + 1);
+    if constexpr (DT == DT_BF16) {
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        const int g = c * CH + j;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[c & 1][j]),
+                                                            __builtin_bit_cast(bf16x8, bq[cb][g]),
+                                                            g == 0 ? init : acc[cb], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < CH; j += 2) {
+        const int g = c * CH + j;
+        const u32x4& a0 = fa[c & 1][j];
+        const u32x4& a1 = fa[c & 1][j + 1];
+        i32x8 A = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const u32x4& b0 = bq[cb][g];
+          const u32x4& b1 = bq[cb][g + 1];
+          i32x8 B = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+          acc[cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, B, g == 0 ? init : acc[cb], 0, 0, 0, sa, 0,
+                                                                     sb[cb]);
+        }
+      }
+    }
+  });
+}
+
 // A bin's running winner is a "unit": either one exact row or a group of 4
 // consecutive rows (one lane's accumulators 4k..4k+3) whose exact row is resolved
 // later from the prepared rows.  Units are keyed u = 2*start + is_group (unsigned,
@@ -281,12 +349,12 @@ __device__ __forceinline__ void mma_tile_interleaved(f32x16 (&acc)[NCB], const T
 // take it from a scalar; merge_halves adds the offset back.
 constexpr unsigned kNoUnit = 0xFFFFFFFFu;
 
-// max of three finite floats in one instruction (the compiler's own max3 matching
-// pairs the operands differently and leaves a third max)
-__device__ __forceinline__ float max3f(float a, float b, float c) {
-  float r;
-  asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-  return r;
+// max(best, a0..a3) nested so that the compiler's max3 matching (outermost first)
+// yields two v_max3_f32: max3(best, a3, max3(a0, a1, a2)).  Plain code rather than
+// asm, so that the compiler also inserts the wait states that reading a matrix
+// instruction's fresh result needs.
+__device__ __forceinline__ float max5f(float best, float a0, float a1, float a2, float a3) {
+  return fmaxf(best, fmaxf(a3, fmaxf(a0, fmaxf(a1, a2))));
 }
 
 // merge the two lane halves' (value, unit) of one query: larger value, then lower unit
@@ -424,69 +492,38 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   int cur_bin = (int)b0;
   BinCursor cursor = make_cursor(b0, N, L);
 
-  // Software pipeline over the chunk's tiles.  Step t: the tile loads run S tiles
-  // ahead (direct global->LDS); the fragments of tile t+1 are read from LDS and
-  // its matrix instructions issued while tile t's scores are folded into the bins,
-  // in one scheduling region.  Past the end the pipeline computes on stale LDS
-  // data whose results are never used.
-#pragma unroll
-  for (int s = 0; s < S; ++s)
-    if (t_first + s <= t_last) load_tile<NG>(db_tiles + (int64_t)(t_first + s) * TB, lds + s * G::kLdsBytes, plan, wave, lane);
-  TileRegs<NG> fr;
-  f32x16 acc_a[NCB], acc_b[NCB];
-  if (t_last - t_first >= S - 1) wait_vmcnt<(S - 1) * G::kLoads>(); else wait_vmcnt<0>();
-  lds_barrier();
-  if (active) {
-    read_tile<NG>(fr, buf(t_first));
-    mma_tile<DT, NG, NCB>(acc_a, fr, bq, sb);
-  }
-
-  auto step = [&](int t, f32x16 (&acc_c)[NCB], f32x16 (&acc_n)[NCB]) {
-    if (t + 1 <= t_last) {
-      // tile t+1 has landed once at most min(S-2, t_last-t-1) later tiles are pending
-      if (t_last - t - 1 >= S - 2) wait_vmcnt<(S - 2) * G::kLoads>(); else wait_vmcnt<0>();
-    }
-    lds_barrier();
-    // tile t's fragments were read in the previous step: its buffer takes tile t+S
-    if (t + S <= t_last) load_tile<NG>(db_tiles + (int64_t)(t + S) * TB, buf(t), plan, wave, lane);
-    if (!active) return;
-    const int t0 = t << 5;
-    const unsigned gu0 = 2u * (unsigned)t0 + 1u;  // lane-local unit of accumulator group 0 (uniform)
-    float nbv[NCB];
-    unsigned nbu[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      nbv[cb] = bv[cb];
-      nbu[cb] = bu[cb];
-    }
-    read_tile<NG>(fr, buf(t + 1));
-    __builtin_amdgcn_sched_barrier(0);
-    // unit u: accumulator group k = u / NCB (rows t0 + 8k + 4h + 0..3) of column block
-    // cb = u % NCB of tile t, against the running best (groups in row order)
-    mma_tile_interleaved<DT, NG, NCB>(acc_n, fr, bq, sb, [&](auto pc) {
+  // Bin update of one tile, two units at a time: unit u = accumulator group
+  // k = u / NCB (rows t0 + 8k + 4h + 0..3) of column block cb = u % NCB, against the
+  // running best (groups in row order).
+  auto unit_pair = [&](auto pc, f32x16 (&acc_c)[NCB], float (&nbv)[NCB], unsigned (&nbu)[NCB], unsigned gu0) {
       constexpr int pr = decltype(pc)::value;
       constexpr int uA = 2 * pr, uB = 2 * pr + 1;
       constexpr int kA = uA / NCB, cA = uA % NCB, kB = uB / NCB, cB = uB % NCB;
       // two max3 fold a group into the running best; it changed iff the group won
-      const float mA = max3f(acc_c[cA][4 * kA], acc_c[cA][4 * kA + 1], acc_c[cA][4 * kA + 2]);
-      const float mB = max3f(acc_c[cB][4 * kB], acc_c[cB][4 * kB + 1], acc_c[cB][4 * kB + 2]);
+      const f32x16& xA = acc_c[cA];
+      const f32x16& xB = acc_c[cB];
       if constexpr (cA != cB) {  // two column blocks: independent states
-        const float nA = max3f(mA, acc_c[cA][4 * kA + 3], nbv[cA]);
-        const float nB = max3f(mB, acc_c[cB][4 * kB + 3], nbv[cB]);
+        const float nA = max5f(nbv[cA], xA[4 * kA], xA[4 * kA + 1], xA[4 * kA + 2], xA[4 * kA + 3]);
+        const float nB = max5f(nbv[cB], xB[4 * kB], xB[4 * kB + 1], xB[4 * kB + 2], xB[4 * kB + 3]);
         const bool wA = nA > nbv[cA], wB = nB > nbv[cB];
         nbu[cA] = wA ? gu0 + 16u * kA : nbu[cA];
         nbu[cB] = wB ? gu0 + 16u * kB : nbu[cB];
         nbv[cA] = nA;
         nbv[cB] = nB;
       } else {  // one column block: groups kA < kB update the same state in order
-        const float nA = max3f(mA, acc_c[cA][4 * kA + 3], nbv[cA]);
-        const float nB = max3f(mB, acc_c[cB][4 * kB + 3], nA);
+        const float nA = max5f(nbv[cA], xA[4 * kA], xA[4 * kA + 1], xA[4 * kA + 2], xA[4 * kA + 3]);
+        const float nB = max5f(nA, xB[4 * kB], xB[4 * kB + 1], xB[4 * kB + 2], xB[4 * kB + 3]);
         const bool wA = nA > nbv[cA], wB = nB > nA;
         nbu[cA] = wA ? gu0 + 16u * kA : nbu[cA];
         nbu[cA] = wB ? gu0 + 16u * kB : nbu[cA];
         nbv[cA] = nB;
       }
-    });
+  };
+
+  // Everything after a tile's scores are folded into (nbv, nbu): the fast path,
+  // the one-boundary masked path and the row walk, bin flushes.
+  auto finish = [&](int t0, f32x16 (&acc_c)[NCB], float (&nbv)[NCB], unsigned (&nbu)[NCB]) {
+    const unsigned gu0 = 2u * (unsigned)t0 + 1u;
     // materialise the update here, inside the region with the MFMAs, rather than
     // letting the compiler sink it into the (rarely not taken) fast branch below
 #pragma unroll
@@ -639,10 +676,82 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       }
     }
   };
-  for (int t = t_first; t <= t_last; t += 2) {
-    step(t, acc_a, acc_b);
-    if (t + 1 > t_last) break;
-    step(t + 1, acc_b, acc_a);
+
+  if constexpr (kSingleAcc<DT, NG>()) {
+    // Large depth: one accumulator set (the double-buffered form needs more than the
+    // 256 VGPRs of two waves per SIMD).  Step t: wait for tile t, refill the buffer
+    // of tile t-1 with tile t+S-1, then the tile's matrix instructions (fragments
+    // read in chunks behind them) and its bin update; the other wave of the SIMD
+    // runs its matrix instructions meanwhile.
+#pragma unroll
+    for (int s2 = 0; s2 < S - 1; ++s2)
+      if (t_first + s2 <= t_last) load_tile<NG>(db_tiles + (int64_t)(t_first + s2) * TB, lds + s2 * G::kLdsBytes, plan, wave, lane);
+    f32x16 acc[NCB];
+    for (int t = t_first; t <= t_last; ++t) {
+      // tiles issued so far: up to min(t + S - 2, t_last); tile t has landed once the
+      // later ones are the only loads pending
+      if (t_last - t >= S - 2) wait_vmcnt<(S - 2) * G::kLoads>(); else wait_vmcnt<0>();
+      lds_barrier();
+      if (t + S - 1 <= t_last) load_tile<NG>(db_tiles + (int64_t)(t + S - 1) * TB, buf(t + S - 1), plan, wave, lane);
+      if (!active) continue;
+      const int t0 = t << 5;
+      const unsigned gu0 = 2u * (unsigned)t0 + 1u;
+      mma_tile_chunked<DT, NG, NCB>(acc, buf(t), bq, sb);
+      float nbv[NCB];
+      unsigned nbu[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        nbv[cb] = bv[cb];
+        nbu[cb] = bu[cb];
+      }
+      static_for<0, 2 * NCB>([&](auto pc) { unit_pair(pc, acc, nbv, nbu, gu0); });
+      finish(t0, acc, nbv, nbu);
+    }
+  } else {
+    // Software pipeline over the chunk's tiles.  Step t: the tile loads run S tiles
+    // ahead (direct global->LDS); the fragments of tile t+1 are read from LDS and
+    // its matrix instructions issued while tile t's scores are folded into the bins,
+    // in one scheduling region.  Past the end the pipeline computes on stale LDS
+    // data whose results are never used.
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      if (t_first + s <= t_last) load_tile<NG>(db_tiles + (int64_t)(t_first + s) * TB, lds + s * G::kLdsBytes, plan, wave, lane);
+    TileRegs<NG> fr;
+    f32x16 acc_a[NCB], acc_b[NCB];
+    if (t_last - t_first >= S - 1) wait_vmcnt<(S - 1) * G::kLoads>(); else wait_vmcnt<0>();
+    lds_barrier();
+    if (active) {
+      read_tile<NG>(fr, buf(t_first));
+      mma_tile<DT, NG, NCB>(acc_a, fr, bq, sb);
+    }
+    auto step = [&](int t, f32x16 (&acc_c)[NCB], f32x16 (&acc_n)[NCB]) {
+      if (t + 1 <= t_last) {
+        // tile t+1 has landed once at most min(S-2, t_last-t-1) later tiles are pending
+        if (t_last - t - 1 >= S - 2) wait_vmcnt<(S - 2) * G::kLoads>(); else wait_vmcnt<0>();
+      }
+      lds_barrier();
+      // tile t's fragments were read in the previous step: its buffer takes tile t+S
+      if (t + S <= t_last) load_tile<NG>(db_tiles + (int64_t)(t + S) * TB, buf(t), plan, wave, lane);
+      if (!active) return;
+      const int t0 = t << 5;
+      const unsigned gu0 = 2u * (unsigned)t0 + 1u;  // lane-local unit of accumulator group 0 (uniform)
+      float nbv[NCB];
+      unsigned nbu[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        nbv[cb] = bv[cb];
+        nbu[cb] = bu[cb];
+      }
+      read_tile<NG>(fr, buf(t + 1));
+      __builtin_amdgcn_sched_barrier(0);
+      mma_tile_interleaved<DT, NG, NCB>(acc_n, fr, bq, sb, [&](auto pc) { unit_pair(pc, acc_c, nbv, nbu, gu0); });
+      finish(t0, acc_c, nbv, nbu);
+    };
+    for (int t = t_first; t <= t_last; t += 2) {
+      step(t, acc_a, acc_b);
+      if (t + 1 > t_last) break;
+      step(t + 1, acc_b, acc_a);
+    }
   }
 }
 
@@ -712,6 +821,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
       case 8 * 4 + 1: run_group_item<DT, 8, 1>(gd, it, lds); break;
       case 8 * 4 + 2: run_group_item<DT, 8, 2>(gd, it, lds); break;
       case 16 * 4 + 1: run_group_item<DT, 16, 1>(gd, it, lds); break;
+      case 16 * 4 + 2: run_group_item<DT, 16, 2>(gd, it, lds); break;
       default: break;
     }
   }

@@ -62,6 +62,8 @@ CASES = [
     ("l2", 200, 3000, 64, 10, 80, "bf16"),         # bins of 37-38 rows: one boundary per tile
     ("mips", 100, 2000, 128, 5, 45, "fp8"),        # bins of 44-45 rows
     ("cosine", 64, 4100, 128, 10, 120, "fp32"),    # bins of 34-35 rows, ragged tail tile
+    ("mips", 300, 3000, 192, 10, 50, "bf16"),      # depth 192: the single-accumulator form
+    ("l2", 200, 2500, 256, 10, 40, "bf16"),        # depth 256, L2, bins of 62-63 rows
 ]
 
 
