@@ -505,7 +505,7 @@ knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
     g.q_tiles_n = g.n_qb * QB / kTileRows;
     g.n_chunks = ceil_div(g.L, g.bins_per_chunk);
     p->max_ng = std::max(p->max_ng, db->ng);
-    p->lds_bytes = std::max(p->lds_bytes, fused_lds_bytes(db->ng, g.ncb));
+    p->lds_bytes = std::max(p->lds_bytes, fused_lds_bytes(p->compute, db->ng, g.ncb));
     if (hipMalloc(&g.q_tiles, (size_t)(g.q_tiles_n * tile_bytes(db->ng))) != hipSuccess ||
         hipMalloc(&g.binV, sizeof(float) * (size_t)std::max<int64_t>(1, g.M * g.L)) != hipSuccess ||
         hipMalloc(&g.binA, sizeof(int32_t) * (size_t)std::max<int64_t>(1, g.M * g.L)) != hipSuccess)

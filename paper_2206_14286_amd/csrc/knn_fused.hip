@@ -56,13 +56,29 @@ struct TileGeom {
   static constexpr int kLoads = kPerWave + 1;                               // + one aux load per wave
   static constexpr int kMainBytes = kPerWave * 64 * kWaves * 16;            // incl. landing pad
   static constexpr int kLdsBytes = kMainBytes + kAuxBytes;
-  // pipeline depth: deep for the short low-precision tiles, double buffering for FP32-size tiles
-  static constexpr int kStages = NG <= 8 ? 4 : 2;
 };
 
-template <int NG>
+// Depths at which the kernel keeps one accumulator set (BF16 from 128 up; see
+// run_item): fewer registers, so two or three waves per SIMD overlap one another's
+// bin updates instead of one wave overlapping its own.  FP32 keeps the
+// double-buffered form: its matrix instructions are long enough that one wave per
+// SIMD keeps the unit busy.
+template <int DT, int NG>
+constexpr bool kSingleAcc() {
+  return DT == DT_BF16 && NG >= 8;
+}
+
+// LDS ring depth: 2 for the single-accumulator form (each step refills the buffer
+// freed by the previous one; three workgroups per CU fit), 4 for the short
+// double-buffered tiles, 2 for FP32-size tiles
+template <int DT, int NG>
+constexpr int stages() {
+  return kSingleAcc<DT, NG>() ? 2 : (NG <= 8 ? 4 : 2);
+}
+
+template <int DT, int NG>
 constexpr int lds_bytes() {
-  return TileGeom<NG>::kStages * TileGeom<NG>::kLdsBytes + kWaves * kStageWords * 4;
+  return stages<DT, NG>() * TileGeom<NG>::kLdsBytes + kWaves * kStageWords * 4;
 }
 
 // wait until at most N vector-memory loads of this wave are outstanding
@@ -272,14 +288,6 @@ __device__ __forceinline__ void mma_tile_interleaved(f32x16 (&acc)[NCB], const T
   });
 }
 
-// Depths whose double-buffered form would exceed two waves' registers per SIMD use
-// one accumulator set (FP32 keeps the double-buffered form: its matrix instructions
-// are long enough that one wave per SIMD keeps the unit busy).
-template <int DT, int NG>
-constexpr bool kSingleAcc() {
-  return DT != DT_F32 && NG >= 12;
-}
-
 // acc[cb] = init + the tile's products, with the A fragments read from LDS in chunks
 // of 4 groups, each chunk's reads issued before the previous chunk's matrix
 // instructions (2 x 4 fragment registers instead of NG).
@@ -452,7 +460,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
                                          int64_t q0, int64_t b0, int64_t b1, float sign, float* __restrict__ outV,
                                          int32_t* __restrict__ outA, int64_t ldo, unsigned char* lds) {
   using G = TileGeom<NG>;
-  constexpr int S = G::kStages;
+  constexpr int S = stages<DT, NG>();
   static_assert((S & (S - 1)) == 0 && S >= 2, "stages: a power of two >= 2");
   constexpr int64_t TB = (int64_t)NG * 1024 + kAuxBytes;
   const int lane = threadIdx.x & 63;
@@ -756,10 +764,11 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
 }
 
 // Occupancy: the short FP8 tiles have the least matrix work per tile to hide the bin
-// update behind, so their kernels are held to 3 waves per SIMD (<= 168 VGPRs).
+// update behind, and the BF16 depth-128 kernel overlaps three waves' bin updates;
+// both are held to 3 waves per SIMD (<= 168 VGPRs).
 template <int DT, int NG>
 constexpr int min_waves() {
-  return (DT == DT_FP8 && NG <= 4) ? 3 : 1;
+  return ((DT == DT_FP8 && NG <= 4) || (DT == DT_BF16 && NG == 8)) ? 3 : 1;
 }
 
 template <int DT, int NG, int NCB>
@@ -782,7 +791,7 @@ hipError_t launch_one(const FusedParams& p, hipStream_t s) {
   (void)hipGetLastError();  // clear any stale error so the check below sees this launch only
   const int64_t per_xcd = ceil_div(p.n_chunks, 8);
   const int64_t grid = 8 * per_xcd * p.n_qb;
-  constexpr int lb = lds_bytes<NG>();
+  constexpr int lb = lds_bytes<DT, NG>();
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<DT, NG, NCB>),
@@ -829,18 +838,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 
 }  // namespace
 
-int fused_lds_bytes(int ng, int ncb) {
+int fused_lds_bytes(int dt, int ng, int ncb) {
   (void)ncb;
-  switch (ng) {
-    case 2: return lds_bytes<2>();
-    case 4: return lds_bytes<4>();
-    case 6: return lds_bytes<6>();
-    case 8: return lds_bytes<8>();
-    case 12: return lds_bytes<12>();
-    case 16: return lds_bytes<16>();
-    case 24: return lds_bytes<24>();
-    default: return lds_bytes<32>();
-  }
+#define KNN_LDS_CASE(D_)                 \
+  if (dt == D_) switch (ng) {            \
+      case 2: return lds_bytes<D_, 2>();   \
+      case 4: return lds_bytes<D_, 4>();   \
+      case 6: return lds_bytes<D_, 6>();   \
+      case 8: return lds_bytes<D_, 8>();   \
+      case 12: return lds_bytes<D_, 12>(); \
+      case 16: return lds_bytes<D_, 16>(); \
+      case 24: return lds_bytes<D_, 24>(); \
+      default: return lds_bytes<D_, 32>(); \
+    }
+  KNN_LDS_CASE(DT_F32)
+  KNN_LDS_CASE(DT_BF16)
+  KNN_LDS_CASE(DT_FP8)
+#undef KNN_LDS_CASE
+  return lds_bytes<DT_F32, 32>();
 }
 
 #define KNN_FUSED_CASES(X)                                                                                     \

@@ -84,7 +84,7 @@ struct FusedParams {
 // ncb: 32-query column blocks per wave (1 or 2)
 hipError_t launch_fused(int dt, int ng, int ncb, const FusedParams& p, hipStream_t s);
 bool fused_supported(int dt, int ng, int ncb);
-int fused_lds_bytes(int ng, int ncb);
+int fused_lds_bytes(int dt, int ng, int ncb);
 
 // ---- persistent batched distance kernel
 struct WorkItem {      // one (database group, query block, bin chunk) unit
