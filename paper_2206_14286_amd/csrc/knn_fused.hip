@@ -704,7 +704,11 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       if (!active) continue;
       const int t0 = t << 5;
       const unsigned gu0 = 2u * (unsigned)t0 + 1u;
+      // a wave issuing its matrix instructions goes first, so the SIMD's other waves
+      // fill the gaps with their bin updates instead of delaying the matrix unit
+      __builtin_amdgcn_s_setprio(1);
       mma_tile_chunked<DT, NG, NCB>(acc, buf(t), bq, sb);
+      __builtin_amdgcn_s_setprio(0);
       float nbv[NCB];
       unsigned nbu[NCB];
 #pragma unroll
