@@ -58,14 +58,14 @@ struct TileGeom {
   static constexpr int kLdsBytes = kMainBytes + kAuxBytes;
 };
 
-// Depths at which the kernel keeps one accumulator set (BF16 from 128 up; see
-// run_item): fewer registers, so two or three waves per SIMD overlap one another's
-// bin updates instead of one wave overlapping its own.  FP32 keeps the
-// double-buffered form: its matrix instructions are long enough that one wave per
-// SIMD keeps the unit busy.
+// Depths at which the kernel keeps one accumulator set (BF16 from depth 128 up,
+// FP8 at depths 128 and 256; see run_item): fewer registers, so two or three waves
+// per SIMD overlap one another's bin updates instead of one wave overlapping its
+// own.  FP32 keeps the double-buffered form: its matrix instructions are long
+// enough that one wave per SIMD keeps the unit busy.
 template <int DT, int NG>
 constexpr bool kSingleAcc() {
-  return DT == DT_BF16 && NG >= 8;
+  return (DT == DT_BF16 && NG >= 8) || (DT == DT_FP8 && NG % 4 == 0);
 }
 
 // LDS ring depth: 2 for the single-accumulator form (each step refills the buffer
@@ -454,7 +454,9 @@ __device__ __forceinline__ BinCursor make_cursor(int64_t b, int64_t N, int64_t L
   return c;
 }
 
-template <int DT, int NG, int NCB>
+// kPrio: raise the wave priority while a wave issues a tile's matrix instructions
+// (pays off with three waves per SIMD, costs with two)
+template <int DT, int NG, int NCB, bool kPrio>
 __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_tiles,
                                          const unsigned char* __restrict__ q_tiles, int64_t N, int64_t L, int64_t M,
                                          int64_t q0, int64_t b0, int64_t b1, float sign, float* __restrict__ outV,
@@ -706,9 +708,9 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       const unsigned gu0 = 2u * (unsigned)t0 + 1u;
       // a wave issuing its matrix instructions goes first, so the SIMD's other waves
       // fill the gaps with their bin updates instead of delaying the matrix unit
-      __builtin_amdgcn_s_setprio(1);
+      if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
       mma_tile_chunked<DT, NG, NCB>(acc, buf(t), bq, sb);
-      __builtin_amdgcn_s_setprio(0);
+      if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
       float nbv[NCB];
       unsigned nbu[NCB];
 #pragma unroll
@@ -786,7 +788,7 @@ void fused_kernel(FusedParams p) {
   if (chunk >= p.n_chunks) return;
   const int64_t b0 = chunk * p.bins_per_chunk;
   const int64_t b1 = (b0 + p.bins_per_chunk) < p.L ? (b0 + p.bins_per_chunk) : p.L;
-  run_item<DT, NG, NCB>(p.db_tiles, p.q_tiles, p.N, p.L, p.M, (int64_t)qb * (kWaves * 32 * NCB), b0, b1, p.out_sign, p.binV,
+  run_item<DT, NG, NCB, (min_waves<DT, NG>() >= 3)>(p.db_tiles, p.q_tiles, p.N, p.L, p.M, (int64_t)qb * (kWaves * 32 * NCB), b0, b1, p.out_sign, p.binV,
                         p.binA, p.ldo, lds);
 }
 
@@ -810,7 +812,7 @@ hipError_t launch_one(const FusedParams& p, hipStream_t s) {
 // ---------------------------------------------------------------- persistent batched form
 template <int DT, int NG, int NCB>
 __device__ __forceinline__ void run_group_item(const GroupDesc& gd, const WorkItem& it, unsigned char* lds) {
-  run_item<DT, NG, NCB>(gd.db_tiles, gd.q_tiles, gd.N, gd.L, gd.M, (int64_t)it.qb * (kWaves * 32 * NCB), it.b0,
+  run_item<DT, NG, NCB, false>(gd.db_tiles, gd.q_tiles, gd.N, gd.L, gd.M, (int64_t)it.qb * (kWaves * 32 * NCB), it.b0,
                         it.b1, gd.out_sign, gd.binV, gd.binA, gd.ldo, lds);
 }
 
