@@ -270,6 +270,71 @@ def row_mips_backward(torch, knn, datagen, steps):
     return res
 
 
+def row_approx(torch, knn, datagen, reps=10):
+    """The approx_max_k op on a score matrix the caller holds (1024 x 2^20, the shape of
+    the paper's reshape + argmax comparison), bins only (L = 128) and with the top-10:
+    bound by HBM bandwidth, one read of the matrix per call."""
+    w = datagen.ABLATION
+    M, N, L = w["M"], w["N"], w["L"]
+    out = {"workload": "approx_max_k", "rows": M, "cols": N, "L": L}
+    for dt in ("fp32", "bf16"):
+        S = datagen.normal_device(M, N, seed=77, dtype=torch.bfloat16 if dt == "bf16" else None)
+        nbytes = S.numel() * S.element_size()
+        ob = (torch.empty((M, L), dtype=torch.float32, device="cuda"), torch.empty((M, L), dtype=torch.int32, device="cuda"))
+        ok = (torch.empty((M, 10), dtype=torch.float32, device="cuda"), torch.empty((M, 10), dtype=torch.int32, device="cuda"))
+        tb = time_kernel_events(lambda: knn.approx_top_k(S, 10, L=L, aggregate_to_topk=False, out=ob), reps)
+        tk = time_kernel_events(lambda: knn.approx_top_k(S, 10, L=L, out=ok), reps)
+        out[dt] = {"bins_ms": tb * 1e3, "bins_gb_s": nbytes / tb / 1e9, "bins_frac_of_hbm": nbytes / tb / 1e9 / HBM_GBS,
+                   "topk_ms": tk * 1e3, "topk_gb_s": nbytes / tk / 1e9}
+        del S
+        torch.cuda.empty_cache()
+    # the same reduction down the columns of the transposed matrix (reduction_dimension 0)
+    S = datagen.normal_device(N, M, seed=77)
+    nbytes = S.numel() * S.element_size()
+    ob = (torch.empty((L, M), dtype=torch.float32, device="cuda"), torch.empty((L, M), dtype=torch.int32, device="cuda"))
+    tb = time_kernel_events(lambda: knn.approx_top_k(S, 10, reduction_dimension=0, L=L, aggregate_to_topk=False,
+                                                     out=ob), reps)
+    out["fp32_dim0"] = {"bins_ms": tb * 1e3, "bins_gb_s": nbytes / tb / 1e9,
+                        "bins_frac_of_hbm": nbytes / tb / 1e9 / HBM_GBS}
+    del S
+    torch.cuda.empty_cache()
+    return out
+
+
+def row_ablation(torch, knn, datagen, reps=5):
+    """The paper's comparison of the fused op with a dense GEMM + reshape + argmax (queries
+    1024 x 128, database 2^20 x 128, L = 128, MIPS, FP32; also BF16): the fused distance +
+    bin-reduce kernel against (a) a torch matmul (hipBLASLt) materialising the 1024 x 2^20
+    scores, then this library's bin reduce on them, and (b) the same matmul, then torch's
+    own reshape + max per bin, as the paper's listing does."""
+    w = datagen.ABLATION
+    M, N, D, L = w["M"], w["N"], w["D"], w["L"]
+    Q = datagen.normal_device(M, D, seed=78)
+    X = datagen.normal_device(N, D, seed=79)
+    out = {"workload": "ablation", "M": M, "N": N, "D": D, "L": L}
+    for dt in ("fp32", "bf16"):
+        tdt = torch.float32 if dt == "fp32" else torch.bfloat16
+        Qc, Xc = Q.to(tdt), X.to(tdt)
+        db = knn.Database(Xc, "mips", dt)
+        qbuf = db.prepare_queries(Qc)
+        bins = (torch.empty((M, L), dtype=torch.float32, device="cuda"), torch.empty((M, L), dtype=torch.int32, device="cuda"))
+        t_fused = time_kernel_events(lambda: db.partial_reduce(qbuf, M, L, out=bins, resolve=True), reps)
+        S = torch.empty((M, N), dtype=tdt, device="cuda")
+        XT = Xc.t().contiguous()
+        t_gemm = time_kernel_events(lambda: torch.matmul(Qc, XT, out=S), reps)
+        t_ours = time_kernel_events(lambda: knn.approx_top_k(S, 1, L=L, aggregate_to_topk=False, out=bins), reps)
+        t_torch = time_kernel_events(lambda: torch.max(S.view(M, L, N // L), dim=2), reps)
+        flops = 2.0 * M * N * D
+        out[dt] = {"fused_ms": t_fused * 1e3, "fused_tflops": flops / t_fused / 1e12,
+                   "gemm_ms": t_gemm * 1e3, "gemm_tflops": flops / t_gemm / 1e12,
+                   "unfused_ours_ms": (t_gemm + t_ours) * 1e3, "unfused_reshape_argmax_ms": (t_gemm + t_torch) * 1e3,
+                   "speedup_vs_unfused_ours": (t_gemm + t_ours) / t_fused,
+                   "speedup_vs_reshape_argmax": (t_gemm + t_torch) / t_fused}
+        del db, qbuf, S, XT, Qc, Xc
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,7 +346,7 @@ def main():
     ap.add_argument("--recall-sample", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--rows", default="fp8_equal_recall,mips_small,cosine_glove,batched,mips_backward",
+    ap.add_argument("--rows", default="fp8_equal_recall,mips_small,cosine_glove,batched,mips_backward,approx,ablation",
                     help="other measurements to add to the line (empty: none)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size kernel for "
@@ -394,7 +459,9 @@ def main():
     for name_r, fn in (("mips_small", lambda: row_mips_small(torch, knn, datagen)),
                        ("cosine_glove", lambda: row_cosine_glove(torch, knn, datagen, oracle, 5, 1)),
                        ("batched", lambda: row_batched(torch, knn, datagen, 3)),
-                       ("mips_backward", lambda: row_mips_backward(torch, knn, datagen, 3))):
+                       ("mips_backward", lambda: row_mips_backward(torch, knn, datagen, 3)),
+                       ("approx", lambda: row_approx(torch, knn, datagen)),
+                       ("ablation", lambda: row_ablation(torch, knn, datagen))):
         if name_r in rows:
             log("workload", name_r)
             others[name_r] = fn()

@@ -197,6 +197,47 @@ knn_status knn_plan_info(const knn_plan* plan, int64_t* L, int32_t* qblock, int6
 
 knn_status knn_plan_destroy(knn_plan* plan);
 
+/* ------------------------------------------------------------------ approx_max_k on scores */
+
+/* The number of bins the op below uses for a slice of n scores when L is not given
+ * (App. A.1, the op's options): L_eval = knn_bins_for_recall(K, recall_target, n_eval)
+ * with n_eval = input_size_override if > 0, else n.  With an override the slice is
+ * read as a part of a longer one (a shard of a sharded reduction) and gets the same
+ * bin density: L = ceil(L_eval * n / n_eval).  The result is clamped to [K, n].
+ * Returns -1 for n < 1, K < 1, K > n or recall_target outside (0, 1). */
+int64_t knn_approx_bins(int64_t n, int32_t K, double recall_target, int64_t input_size_override);
+
+/* PartialReduce (Sec. 5, Algorithm 1) over a score matrix the caller already has,
+ * without the distance GEMM, optionally followed by the exact top-K (ExactRescoring):
+ * the approx_max_k / approx_min_k op with the options of App. A.1.
+ *   scores         device, rows x cols, row-major with leading dimension ld >= cols
+ *                  (element (i, j) at scores[i * ld + j]), type dtype (KNN_F32 or
+ *                  KNN_BF16), aligned to its element size
+ *   reduction_dim  1 (or -1, the last dimension): each row is a slice of n = cols
+ *                  scores, B = rows slices; 0: each column is a slice of n = rows
+ *                  scores, B = cols slices
+ *   K              results per slice, 1 <= K <= n (K <= 1024 when aggregating)
+ *   L              bins per slice, K <= L <= n; L <= 0 derives it from recall_target
+ *                  and input_size_override (knn_approx_bins)
+ *   minimize       0: larger is better (approx_max_k); 1: smaller (approx_min_k)
+ *   aggregate_to_topk
+ *                  1: out_val/out_idx receive the best K bin winners of each slice,
+ *                     best first, ties by lower index;
+ *                  0: they receive all L bin winners of each slice (bin b holds slice
+ *                     positions [floor(b n / L), floor((b + 1) n / L)); the lowest
+ *                     position wins ties)
+ *   out_val, out_idx  device FP32 and int32, laid out like the input with the reduced
+ *                  dimension replaced by the result count R (K or L): B x R row-major
+ *                  for reduction_dim 1, R x B row-major for reduction_dim 0.  Indices
+ *                  are positions along the reduced dimension; values are the scores
+ *                  widened to FP32 (a -0 score may come back as +0).
+ * Bit-exact: no arithmetic is done on the scores.  B = 0 is a no-op.  With
+ * aggregate_to_topk the B x L bins are a stream-ordered temporary (hipMallocAsync). */
+knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_t rows, int64_t cols, int64_t ld,
+                            int32_t reduction_dim, int32_t K, double recall_target, int64_t input_size_override,
+                            int64_t L, int32_t minimize, int32_t aggregate_to_topk, float* out_val,
+                            int32_t* out_idx, void* stream);
+
 /* ------------------------------------------------------------------ backward */
 
 /* Gradient of sum_{i,k} g[i,k] * score(q_i, x_{idx[i,k]}) with the selection held

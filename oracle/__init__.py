@@ -8,6 +8,9 @@ Parts:
   * ``knn_oracle.c`` (FP64, OpenMP over queries): scores, Algorithm 1
     (PartialReduce) on contiguous balanced bins, exact top-K of the bin
     winners, exact K-NN by full sort, dense reference gradients.
+  * ``approx_top_k`` / ``approx_bins``: the approx_max_k op of App. A.1 on a given
+    score matrix (Algorithm 1 along either dimension, optional top-K, the bin count
+    from the recall target and the input-size override).
   * this module: the ctypes wrapper for it, the recall model of Sec. 5.1
     (eq. recall, eq. l:approx and the appendix on the number of bins), the
     exact recall expectation for fixed balanced bins, recall metrics
@@ -167,6 +170,48 @@ def search(Q, X, metric, L: int, K: int, *, bins: bool = False, exact: bool = Fa
     if rc != 0:
         raise ValueError("oracle: invalid sizes (need 1 <= K <= L <= N, D >= 1)")
     return out
+
+
+def approx_bins(n: int, K: int, r: float = 0.95, input_size_override: int = -1) -> int:
+    """Bins of the approx_max_k op for a slice of n scores (App. A.1's options): the recall
+    target fixes L for the evaluated size (eq. l:approx, exact inverse); a positive
+    ``input_size_override`` evaluates that size instead and keeps its bin density for the
+    n scores at hand, L = ceil(L_eval * n / override) (the reading used for shards of a
+    longer reduction); clamped to [K, n]."""
+    n_eval = input_size_override if input_size_override > 0 else n
+    L = bins_for_recall(K, r, n_eval)
+    if input_size_override > 0:
+        L = -((-L * n) // n_eval)
+    return min(max(L, K), n)
+
+
+def approx_top_k(S, K: int, L: int, dim: int = -1, minimize: bool = False, aggregate: bool = True):
+    """The approx_max_k / approx_min_k op on a given score matrix (App. A.1): Algorithm 1
+    over each slice along ``dim`` (rows for dim = 1 or -1, columns for dim = 0), then,
+    with ``aggregate``, the exact top-K of the bin winners (ExactRescoring).  The result
+    keeps the input's layout with the reduced dimension replaced by K (or L); indices are
+    positions along the reduced dimension.  Scores are widened to FP64 exactly."""
+    S = np.asarray(S, np.float64)
+    T = S if dim in (-1, 1) else S.T
+    B, n = T.shape
+    V = np.empty((B, L))
+    A = np.empty((B, L), np.int64)
+    rows = np.arange(B)
+    for b in range(L):
+        # bin b: positions [floor(b n / L), floor((b + 1) n / L)); numpy's argmax / argmin
+        # return the first best position, i.e. the strict comparison scanning upwards.
+        # The bin's first score starts the scan, so a bin of -inf scores (masked-out
+        # entries) still reports its first position.
+        j0, j1 = (b * n) // L, ((b + 1) * n) // L
+        blk = T[:, j0:j1]
+        a = np.argmin(blk, axis=1) if minimize else np.argmax(blk, axis=1)
+        V[:, b] = blk[rows, a]
+        A[:, b] = j0 + a
+    if aggregate:
+        V, A = topk_pairs(V, A, K, minimize)
+    if dim == 0:
+        V, A = V.T, A.T
+    return np.ascontiguousarray(V), np.ascontiguousarray(A)
 
 
 def backward(g, a, Q, X, metric):

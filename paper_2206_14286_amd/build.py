@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libknn_mi355x.so")
 SOURCES = ["knn_prepare.hip", "knn_fused.hip", "knn_select.hip", "knn_resolve.hip", "knn_rerank_backward.hip",
-           "knn_api.cpp"]
+           "knn_approx.hip", "knn_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -27,9 +27,9 @@ FLAGS = [
 ]
 
 
-# per-file extras: the distance kernel assumes finite scores (as the C ABI states), which
-# lets max() of matrix-unit results compile to plain v_max/v_max3 without NaN quieting
-EXTRA = {"knn_fused.hip": ["-fno-honor-nans"]}
+# per-file extras: the distance kernel and the bin reduce over caller scores assume no NaN
+# (as the C ABI states), which lets max() compile to plain v_max/v_max3 without NaN quieting
+EXTRA = {"knn_fused.hip": ["-fno-honor-nans"], "knn_approx.hip": ["-fno-honor-nans"]}
 
 
 def _compile(src: str) -> str:

@@ -465,6 +465,68 @@ extern "C" knn_status knn_backward(const float* g, const int32_t* idx, const voi
   return KNN_OK;
 }
 
+// --------------------------------------------------------------------------- approx_max_k on scores
+extern "C" int64_t knn_approx_bins(int64_t n, int32_t K, double recall_target, int64_t input_size_override) {
+  if (n < 1 || K < 1 || K > n) return -1;
+  const int64_t n_eval = input_size_override > 0 ? input_size_override : n;
+  const int64_t L_eval = knn_bins_for_recall(K, recall_target, n_eval);
+  if (L_eval < 1) return -1;
+  int64_t L = L_eval;
+  if (input_size_override > 0) {
+    // the same bin density as the L_eval bins of the n_eval-long slice this one is part of
+    L = (int64_t)std::ceil((double)L_eval * (double)n / (double)n_eval);
+  }
+  return std::min<int64_t>(std::max<int64_t>(L, K), n);
+}
+
+extern "C" knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_t rows, int64_t cols, int64_t ld,
+                                       int32_t reduction_dim, int32_t K, double recall_target,
+                                       int64_t input_size_override, int64_t L, int32_t minimize,
+                                       int32_t aggregate_to_topk, float* out_val, int32_t* out_idx, void* stream) {
+  g_last_error.clear();
+  if (dtype != KNN_F32 && dtype != KNN_BF16) return fail(KNN_ERR_INVALID, "dtype must be KNN_F32 or KNN_BF16");
+  if (rows < 0 || cols < 0) return fail(KNN_ERR_INVALID, "rows and cols must be >= 0");
+  if (ld < cols || ld < 1) return fail(KNN_ERR_INVALID, "need ld >= max(cols, 1) (ld=%lld)", (long long)ld);
+  if (reduction_dim == -1) reduction_dim = 1;
+  if (reduction_dim != 0 && reduction_dim != 1) return fail(KNN_ERR_INVALID, "reduction_dim must be 0, 1 or -1");
+  if (minimize != 0 && minimize != 1) return fail(KNN_ERR_INVALID, "minimize must be 0 or 1");
+  if (aggregate_to_topk != 0 && aggregate_to_topk != 1) return fail(KNN_ERR_INVALID, "aggregate_to_topk must be 0 or 1");
+  const int64_t n = reduction_dim == 1 ? cols : rows, B = reduction_dim == 1 ? rows : cols;
+  if (n < 1 || n >= (int64_t(1) << 31))
+    return fail(KNN_ERR_INVALID, "the reduced dimension must have 1 .. 2^31 - 1 entries (got %lld)", (long long)n);
+  if (K < 1 || K > n) return fail(KNN_ERR_INVALID, "need 1 <= K <= reduced size (K=%d, n=%lld)", K, (long long)n);
+  if (aggregate_to_topk && K > 1024) return fail(KNN_ERR_INVALID, "K must be <= 1024 (got %d)", K);
+  if (L <= 0) {
+    if (!(recall_target > 0.0 && recall_target < 1.0))
+      return fail(KNN_ERR_INVALID, "recall_target must be in (0, 1)");
+    L = knn_approx_bins(n, K, recall_target, input_size_override);
+  }
+  if (L < K || L > n)
+    return fail(KNN_ERR_INVALID, "need K <= L <= reduced size (K=%d, L=%lld, n=%lld)", K, (long long)L, (long long)n);
+  if (B > 0 && (!scores || !out_val || !out_idx)) return fail(KNN_ERR_INVALID, "scores and outputs must be non-NULL");
+  const size_t esz = dtype == KNN_F32 ? 4 : 2;
+  if (reinterpret_cast<uintptr_t>(scores) % esz != 0) return fail(KNN_ERR_INVALID, "scores must be %zu-byte aligned", esz);
+  if (B == 0) return KNN_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int dt = dtype == KNN_F32 ? DT_F32 : DT_BF16;
+  if (!aggregate_to_topk) {
+    HIP_TRY(launch_approx_bins(scores, dt, rows, cols, ld, reduction_dim, L, minimize != 0, out_val, out_idx, s),
+            "approx bins");
+    return KNN_OK;
+  }
+  DevBuf vbuf, abuf;
+  HIP_TRY(vbuf.alloc(sizeof(float) * (size_t)(B * L), s), "hipMallocAsync (bins)");
+  HIP_TRY(abuf.alloc(sizeof(int32_t) * (size_t)(B * L), s), "hipMallocAsync (bins)");
+  float* V = static_cast<float*>(vbuf.p);
+  int32_t* A = static_cast<int32_t*>(abuf.p);
+  HIP_TRY(launch_approx_bins(scores, dt, rows, cols, ld, reduction_dim, L, minimize != 0, V, A, s), "approx bins");
+  if (reduction_dim == 1)  // bins B x L, results B x K
+    HIP_TRY(launch_select(V, A, B, L, L, K, minimize != 0, out_val, out_idx, K, s), "top-K");
+  else  // bins L x B (bin-major), results K x B
+    HIP_TRY(launch_select(V, A, B, L, 1, K, minimize != 0, out_val, out_idx, 1, s, B, B), "top-K");
+  return KNN_OK;
+}
+
 // --------------------------------------------------------------------------- batched plan
 namespace {
 

@@ -109,8 +109,11 @@ hipError_t launch_fused_persistent(int dt, const GroupDesc* d_groups, const Work
 // ---- exact top-K over candidate lists (ExactRescoring)
 // row r: candidates V[r*ldv + c], A[r*ldv + c] for c < n, in the metric's own sign.
 // out: K per row, best first (smallest first when `minimize`), ties by lower index.
+// es / eo: element strides of the candidates and of the outputs within a row
+// (1 for row-major lists; the column count for lists laid out down the columns).
 hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t n, int64_t ldv, int K,
-                         bool minimize, float* out_val, int32_t* out_idx, int64_t ldout, hipStream_t s);
+                         bool minimize, float* out_val, int32_t* out_idx, int64_t ldout, hipStream_t s,
+                         int64_t es = 1, int64_t eo = 1);
 
 // per-row descriptors (batched select)
 struct SelRow {
@@ -134,6 +137,12 @@ hipError_t launch_select_rows(const SelRow* d_rows, int64_t rows, int max_K, hip
 hipError_t launch_resolve(int dt, int32_t* codes, int64_t rows, int64_t cols, int64_t ld,
                           const unsigned char* q_tiles, const unsigned char* db_tiles, int ng, hipStream_t s);
 hipError_t launch_resolve_rows(int dt, const SelRow* d_rows, int64_t rows, hipStream_t s);
+
+// ---- PartialReduce over a caller's score matrix (rows x cols, leading dimension ld,
+// FP32 or BF16).  dim 1: each row is a slice, bins out B x L (B = rows, n = cols);
+// dim 0: each column is a slice, bins out L x B (B = cols, n = rows).  1 <= L <= n.
+hipError_t launch_approx_bins(const void* S, int dt, int64_t rows, int64_t cols, int64_t ld, int dim, int64_t L,
+                              bool minimize, float* outV, int32_t* outA, hipStream_t s);
 
 // ---- FP32 rerank of Kr candidates per query from the original rows
 hipError_t launch_rerank(const int32_t* cand, int64_t M, int Kr, const void* Q, int q_dt, const void* X,

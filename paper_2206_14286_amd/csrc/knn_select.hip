@@ -20,6 +20,8 @@ namespace {
 constexpr int kSelThreads = 256;
 constexpr int kMaxK = 1024;
 
+// Scores are keyed by float_key(sgn * v + 0): adding +0 turns -0 into +0, so the two
+// zeros tie as they do under the strict comparison of the bin reduce.
 // Candidate indices are rows (>= 0), 4-row group codes (-2 - start/4, resolved
 // later) or -1 (none).  The tie-break key orders them by row: unit u = 2*start +
 // is_group is unique per candidate (bins are disjoint), and the sort uses ~u so
@@ -92,8 +94,10 @@ __device__ __forceinline__ void radix_pass(SelShared& sh, int64_t n, KeyFn key, 
   eqcount = sh.eqcount;
 }
 
+// candidate c of the row is V[c * es], A[c * es]; output e goes to out_*[e * eo]
 __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int32_t* __restrict__ A, int64_t n,
-                           int K, bool minimize, float* __restrict__ out_val, int32_t* __restrict__ out_idx) {
+                           int64_t es, int K, bool minimize, float* __restrict__ out_val,
+                           int32_t* __restrict__ out_idx, int64_t eo) {
   const int tid = threadIdx.x;
   if (K > n) K = (int)n;
   const float sgn = minimize ? -1.f : 1.f;  // rank by sgn * value, larger first
@@ -102,7 +106,7 @@ __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int
   int krem = K, eqcount = 0;
   auto vkey = [&](int64_t c, bool& ok) {
     ok = true;
-    return float_key(sgn * V[c]);
+    return float_key(sgn * V[c * es] + 0.f);
   };
   for (int shift = 24; shift >= 0; shift -= 8) {
     radix_pass(sh, n, vkey, prefix, mask, shift, krem, digit, eqcount);
@@ -117,8 +121,8 @@ __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int
     unsigned p2 = 0, m2 = 0, d2 = 0;
     int kr2 = krem, eq2 = 0;
     auto ikey = [&](int64_t c, bool& ok) {
-      ok = float_key(sgn * V[c]) == T;
-      return unit_lo(A[c]);
+      ok = float_key(sgn * V[c * es] + 0.f) == T;
+      return unit_lo(A[c * es]);
     };
     for (int shift = 24; shift >= 0; shift -= 8) {
       radix_pass(sh, n, ikey, p2, m2, shift, kr2, d2, eq2);
@@ -131,8 +135,8 @@ __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int
   if (tid == 0) sh.count = 0;
   __syncthreads();
   for (int64_t c = tid; c < n; c += kSelThreads) {
-    const unsigned k = float_key(sgn * V[c]);
-    const unsigned lo = unit_lo(A[c]);
+    const unsigned k = float_key(sgn * V[c * es] + 0.f);
+    const unsigned lo = unit_lo(A[c * es]);
     const bool take = (k > T) || (k == T && (all_eq || lo >= T2));
     if (take) {
       int pos = atomicAdd(&sh.count, 1);
@@ -164,20 +168,22 @@ __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int
   for (int i = tid; i < K; i += kSelThreads) {
     const unsigned long long key = sh.keys[i];
     float v = key_float((unsigned)(key >> 32));
-    out_val[i] = sgn * v;
-    out_idx[i] = unit_code((unsigned)(key & 0xFFFFFFFFull));
+    out_val[i * eo] = sgn * v;
+    out_idx[i * eo] = unit_code((unsigned)(key & 0xFFFFFFFFull));
   }
   __syncthreads();
 }
 
 __global__ __launch_bounds__(kSelThreads) void select_kernel(const float* __restrict__ V,
                                                              const int32_t* __restrict__ A, int64_t rows, int64_t n,
-                                                             int64_t ldv, int K, int minimize,
+                                                             int64_t ldv, int64_t es, int K, int minimize,
                                                              float* __restrict__ out_val,
-                                                             int32_t* __restrict__ out_idx, int64_t ldout) {
+                                                             int32_t* __restrict__ out_idx, int64_t ldout,
+                                                             int64_t eo) {
   __shared__ SelShared sh;
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x)
-    select_row(sh, V + r * ldv, A + r * ldv, n, K, minimize != 0, out_val + r * ldout, out_idx + r * ldout);
+    select_row(sh, V + r * ldv, A + r * ldv, n, es, K, minimize != 0, out_val + r * ldout, out_idx + r * ldout,
+               eo);
 }
 
 __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(const SelRow* __restrict__ rows_desc,
@@ -185,7 +191,7 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(const SelRow* 
   __shared__ SelShared sh;
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
     const SelRow d = rows_desc[r];
-    select_row(sh, d.V, d.A, d.n, d.K, d.minimize != 0, d.out_val, d.out_idx);
+    select_row(sh, d.V, d.A, d.n, 1, d.K, d.minimize != 0, d.out_val, d.out_idx, 1);
   }
 }
 
@@ -194,9 +200,9 @@ __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(const SelRow* 
 // workgroup barriers.  Same order as the radix path.
 template <int R>
 __global__ __launch_bounds__(256) void select_wave_kernel(const float* __restrict__ V, const int32_t* __restrict__ A,
-                                                          int64_t rows, int n, int64_t ldv, int K, int minimize,
-                                                          float* __restrict__ out_val, int32_t* __restrict__ out_idx,
-                                                          int64_t ldout) {
+                                                          int64_t rows, int n, int64_t ldv, int64_t es, int K,
+                                                          int minimize, float* __restrict__ out_val,
+                                                          int32_t* __restrict__ out_idx, int64_t ldout, int64_t eo) {
   const int lane = threadIdx.x & 63;
   const float sgn = minimize ? -1.f : 1.f;
   if (K > n) K = n;
@@ -205,15 +211,17 @@ __global__ __launch_bounds__(256) void select_wave_kernel(const float* __restric
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int c = 64 * i + lane;
-      k[i] = c < n ? (((unsigned long long)float_key(sgn * V[r * ldv + c]) << 32) | unit_lo(A[r * ldv + c])) : 0ull;
+      k[i] = c < n ? (((unsigned long long)float_key(sgn * V[r * ldv + c * es] + 0.f) << 32) |
+                      unit_lo(A[r * ldv + c * es]))
+                   : 0ull;
     }
     wave_sort_desc<R>(k, lane);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int e = 64 * i + lane;
       if (e < K) {
-        out_val[r * ldout + e] = sgn * key_float((unsigned)(k[i] >> 32));
-        out_idx[r * ldout + e] = unit_code((unsigned)(k[i] & 0xFFFFFFFFull));
+        out_val[r * ldout + e * eo] = sgn * key_float((unsigned)(k[i] >> 32));
+        out_idx[r * ldout + e * eo] = unit_code((unsigned)(k[i] & 0xFFFFFFFFull));
       }
     }
   }
@@ -222,7 +230,8 @@ __global__ __launch_bounds__(256) void select_wave_kernel(const float* __restric
 }  // namespace
 
 hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t n, int64_t ldv, int K,
-                         bool minimize, float* out_val, int32_t* out_idx, int64_t ldout, hipStream_t s) {
+                         bool minimize, float* out_val, int32_t* out_idx, int64_t ldout, hipStream_t s, int64_t es,
+                         int64_t eo) {
   (void)hipGetLastError();  // report only this call's launch errors
   if (rows == 0) return hipSuccess;
   if (K > kMaxK || K < 1 || n < 1) return hipErrorInvalidValue;
@@ -230,7 +239,8 @@ hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t
     const int64_t want = ceil_div(rows, 4);
     const unsigned grid = (unsigned)(want < 65536 ? want : 65536);
     const int nn = (int)n, mz = minimize ? 1 : 0;
-#define KNN_SELW(R_) select_wave_kernel<R_><<<grid, 256, 0, s>>>(V, A, rows, nn, ldv, K, mz, out_val, out_idx, ldout)
+#define KNN_SELW(R_) \
+  select_wave_kernel<R_><<<grid, 256, 0, s>>>(V, A, rows, nn, ldv, es, K, mz, out_val, out_idx, ldout, eo)
     if (n <= 64)
       KNN_SELW(1);
     else if (n <= 128)
@@ -245,8 +255,8 @@ hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t
     return hipGetLastError();
   }
   const int64_t grid = rows < 65536 ? rows : 65536;
-  select_kernel<<<(unsigned)grid, kSelThreads, 0, s>>>(V, A, rows, n, ldv, K, minimize ? 1 : 0, out_val, out_idx,
-                                                       ldout);
+  select_kernel<<<(unsigned)grid, kSelThreads, 0, s>>>(V, A, rows, n, ldv, es, K, minimize ? 1 : 0, out_val,
+                                                       out_idx, ldout, eo);
   return hipGetLastError();
 }
 

@@ -93,6 +93,34 @@ def targets(m: int, k: int, seed: int) -> np.ndarray:
     return _rng(seed).integers(0, k, size=m).astype(np.int64)
 
 
+def score_matrix(rows: int, cols: int, seed: int, kind: str = "normal") -> np.ndarray:
+    """float32 score matrices for the approx_max_k op on its own:
+    'normal' i.i.d. N(0, 1); 'ints' integers in [-8, 8] (many exact ties); 'zeros' +0 and
+    -0 in equal parts with a few +-1 (ties between the two zeros); 'masked' N(0, 1) with
+    about a quarter of the entries set to -inf (masked-out scores)."""
+    r = _rng(seed)
+    if kind == "normal":
+        return r.standard_normal((rows, cols), dtype=np.float32)
+    if kind == "ints":
+        return r.integers(-8, 9, size=(rows, cols)).astype(np.float32)
+    if kind == "zeros":
+        out = np.where(r.random((rows, cols)) < 0.5, np.float32(0.0), np.float32(-0.0)).astype(np.float32)
+        pick = r.random((rows, cols))
+        out[pick < 0.01] = 1.0
+        out[pick > 0.99] = -1.0
+        return out
+    if kind == "masked":
+        out = r.standard_normal((rows, cols), dtype=np.float32)
+        out[r.random((rows, cols)) < 0.25] = -np.inf
+        return out
+    raise KeyError(kind)
+
+
+# The shape of the paper's comparison of the fused op with a dense GEMM followed by a
+# reshape and an argmax per bin (appendix on the alternative implementation):
+# queries 1024 x 128, database 2^20 x 128, L = 128 bins of 8192 rows, FP32, MIPS.
+ABLATION = dict(M=1024, N=1 << 20, D=128, L=128)
+
 # Databases of the batched workload: (N, D), BF16 N(0, 1) rows, MIPS, K = 10
 BATCHED_DBS = [(100_000, 64), (1_000_000, 96), (4_000_000, 128), (16_000_000, 256)]
 BATCHED_COUNT = 256

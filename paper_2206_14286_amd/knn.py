@@ -64,6 +64,8 @@ def lib():
             "knn_query_prepare": (i32, [P, P, i32, i64, P, ctypes.c_size_t, P]),
             "knn_partial_reduce": (i32, [P, P, i64, i64, P, P, P]),
             "knn_resolve_rows": (i32, [P, P, i64, i64, P, i64, P]),
+            "knn_approx_bins": (i64, [i64, i32, f64, i64]),
+            "knn_approx_top_k": (i32, [P, i32, i64, i64, i64, i32, i32, f64, i64, i64, i32, i32, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -271,6 +273,51 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------------------ approx_max_k on scores
+def approx_bins(n: int, k: int, recall_target: float = 0.95, reduction_input_size_override: int = -1) -> int:
+    """``knn_approx_bins``: the bin count the op uses for a slice of n scores."""
+    return int(lib().knn_approx_bins(int(n), int(k), float(recall_target), int(reduction_input_size_override)))
+
+
+def approx_top_k(scores: torch.Tensor, k: int, reduction_dimension: int = -1, recall_target: float = 0.95,
+                 reduction_input_size_override: int = -1, aggregate_to_topk: bool = True, minimize: bool = False,
+                 L: int | None = None, out=None):
+    """``knn_approx_top_k`` on a 2-D FP32 or BF16 device matrix whose rows may be strided
+    (unit stride along the last dimension).  Returns (values FP32, indices int32) with the
+    reduced dimension replaced by k (aggregate_to_topk) or by the bin count."""
+    if not scores.is_cuda or scores.dim() != 2:
+        raise ValueError("scores must be a 2-D device tensor")
+    if scores.stride(1) != 1:
+        raise ValueError("scores must have unit stride along its last dimension")
+    rows, cols = scores.shape
+    ld = max(int(scores.stride(0)), cols, 1)
+    dim = 1 if reduction_dimension in (-1, 1) else int(reduction_dimension)
+    n, B = (cols, rows) if dim == 1 else (rows, cols)
+    if L is None:
+        L = approx_bins(n, k, recall_target, reduction_input_size_override)
+    R = int(k) if aggregate_to_topk else int(L)
+    shape = (B, R) if dim == 1 else (R, B)
+    if out is None:
+        ov = torch.empty(shape, dtype=torch.float32, device=scores.device)
+        oi = torch.empty(shape, dtype=torch.int32, device=scores.device)
+    else:
+        ov, oi = out
+    _check(lib().knn_approx_top_k(_ptr(scores), _in_dtype(scores), rows, cols, ld, dim, int(k), float(recall_target),
+                                  int(reduction_input_size_override), int(L), int(bool(minimize)),
+                                  int(bool(aggregate_to_topk)), _ptr(ov), _ptr(oi), _stream()))
+    return ov, oi
+
+
+def approx_max_k(scores, k, **kw):
+    """The paper's approx_max_k on a score matrix (App. A.1 options as keywords)."""
+    return approx_top_k(scores, k, minimize=False, **kw)
+
+
+def approx_min_k(scores, k, **kw):
+    """approx_min_k: the same reduction keeping the smallest scores."""
+    return approx_top_k(scores, k, minimize=True, **kw)
 
 
 # ------------------------------------------------------------------------------ backward

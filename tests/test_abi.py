@@ -49,6 +49,39 @@ def test_helpers_match_oracle(K):
     assert K.lib().knn_bin_start(-1, 10, 5) == -1
 
 
+def test_approx_bins_match_oracle(K):
+    for n in (1, 10, 176, 1000, 65536, 1 << 20):
+        for k in (1, 10, 64):
+            if k > n:
+                assert K.lib().knn_approx_bins(n, k, 0.95, -1) == -1
+                continue
+            for over in (-1, n, 4 * n, 3 * n + 1):
+                assert K.approx_bins(n, k, 0.95, over) == oracle.approx_bins(n, k, 0.95, over)
+
+
+def test_approx_top_k_argument_checks(K):
+    lib = K.lib()
+    fake = _p(0x1000)
+    args = dict(dt=0, rows=4, cols=100, ld=100, dim=1, k=5, r=0.95, over=-1, L=10, mn=0, agg=1)
+
+    def call(**kw):
+        a = {**args, **kw}
+        return lib.knn_approx_top_k(fake, a["dt"], a["rows"], a["cols"], a["ld"], a["dim"], a["k"], a["r"],
+                                    a["over"], a["L"], a["mn"], a["agg"], fake, fake, None)
+    assert call(dt=2) == 1
+    assert call(ld=99) == 1
+    assert call(dim=2) == 1
+    assert call(L=4) == 1 and b"K <= L" in lib.knn_last_error()
+    assert call(L=101) == 1
+    assert call(k=101) == 1
+    assert call(k=2000, cols=5000, ld=5000, L=3000) == 1
+    assert call(L=0, r=1.5) == 1
+    assert call(dim=0, k=5, L=10) == 1  # the reduced dimension has 4 entries
+    # no slices: succeeds without touching the device
+    assert call(rows=0) == 0
+    assert call(dim=0, rows=100, cols=0) == 0
+
+
 def test_status_strings(K):
     lib = K.lib()
     assert lib.knn_status_string(0) == b"ok"
