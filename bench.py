@@ -51,9 +51,9 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(compute):
-    """HBM bytes per launch of the distance kernel for `compute`, from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current sources."""
+def _counter_figure(key):
+    """A machine-readable figure of the committed rocprofv3 counter summary of the distance
+    kernel on l2_sift, if the summary was taken on the current sources."""
     if not os.path.exists(COUNTERS_FILE):
         return None
     vals = {}
@@ -61,11 +61,67 @@ def measured_traffic(compute):
         line = line.strip()
         if line.startswith("- source_sha256:"):
             vals["sha"] = line.split(":", 1)[1].strip()
-        elif line.startswith(f"- traffic_bytes_per_launch[{compute}]:"):
-            vals["bytes"] = float(line.split(":", 1)[1].strip())
-    if vals.get("sha") != kernel_source_digest() or "bytes" not in vals:
+        elif line.startswith(f"- {key}:"):
+            vals["v"] = float(line.split(":", 1)[1].strip())
+    if vals.get("sha") != kernel_source_digest() or "v" not in vals:
         return None
-    return vals["bytes"]
+    return vals["v"]
+
+
+def measured_traffic(compute):
+    """HBM bytes per launch of the distance kernel for `compute` (FETCH_SIZE + WRITE_SIZE,
+    scaled by a copy of known size)."""
+    return _counter_figure(f"traffic_bytes_per_launch[{compute}]")
+
+
+def measured_cops(compute):
+    """VALU lane-operations per score of the distance kernel (SQ_INSTS_VALU minus
+    SQ_INSTS_MFMA, times 64 lanes, over M x N scores): the kernel's measured C."""
+    return _counter_figure(f"valu_ops_per_score[{compute}]")
+
+
+def perf_model_rows(line):
+    """The performance model of Sec. 4 (eq. roofline) for every measured launch of the
+    distance kernel in this run, in the layout of Table 2."""
+    from paper_2206_14286_amd import perf_model as pm
+    rows = []
+    c = line["config"]
+
+    def ib(M):
+        return 256 if M > 128 else 128
+
+    forms = {line["dtype"]: {"fused_tflops": line["roofline"]["achieved"], "L": c["L"]}}
+    forms.update(line.get("variants", {}))
+    for comp, r in forms.items():
+        same_L = r["L"] == c["L"]
+        rows.append(pm.entry("l2_sift", comp, "l2", c["M"], c["N"], dpad(c["D"], comp), r["L"], ib(c["M"]),
+                             r["fused_tflops"], measured_traffic(comp) if same_L else None,
+                             measured_cops(comp) if same_L else None))
+    if "fp8_equal_recall" in line:
+        r = line["fp8_equal_recall"]
+        rows.append(pm.entry("l2_sift (FP8 at the FP32 recall)", "fp8", "l2", c["M"], c["N"], dpad(c["D"], "fp8"),
+                             r["L"], ib(c["M"]), r["fused_tflops"]))
+    o = line.get("other_workloads", {})
+    if "mips_small" in o:
+        r = o["mips_small"]
+        rows.append(pm.entry("mips_small (whole call)", "fp32", "mips", r["M"], r["N"], r["D"], r["L"], ib(r["M"]),
+                             r["tflops"]))
+    if "cosine_glove" in o:
+        r = o["cosine_glove"]
+        for comp in ("fp32", "fp8"):
+            if comp in r:
+                rows.append(pm.entry("cosine_glove", comp, "cosine", r["M"], r["N"], dpad(r["D"], comp), r[comp]["L"],
+                                     ib(r["M"]), r[comp]["tflops"]))
+    if "mips_backward" in o:
+        r = o["mips_backward"]
+        rows.append(pm.entry("mips_backward (forward)", "bf16", "mips", r["M"], r["N"], r["D"], r["L"], ib(r["M"]),
+                             r["forward_tflops"]))
+    if "ablation" in o:
+        r = o["ablation"]
+        for comp in ("fp32", "bf16"):
+            rows.append(pm.entry("ablation (fused)", comp, "mips", r["M"], r["N"], r["D"], r["L"], ib(r["M"]),
+                                 r[comp]["fused_tflops"]))
+    return rows
 
 
 def dpad(D, compute):
@@ -433,6 +489,15 @@ def main():
         },
         "variants": {k: v for k, v in results.items() if k != args.compute},
     }
+    # context for the fraction of peak: a large square BF16 GEMM from the vendor library
+    # (hipBLASLt through torch.matmul) on the same GPU, same nominal peak
+    A = torch.randn((8192, 8192), device="cuda").to(torch.bfloat16)
+    Bm = torch.randn((8192, 8192), device="cuda").to(torch.bfloat16)
+    Cm = torch.empty((8192, 8192), device="cuda", dtype=torch.bfloat16)
+    tg = time_kernel_events(lambda: torch.matmul(A, Bm, out=Cm), 20)
+    line["roofline"]["library_gemm_bf16_8192_tflops"] = 2.0 * 8192 ** 3 / tg / 1e12
+    del A, Bm, Cm
+    torch.cuda.empty_cache()
     rows = [r for r in args.rows.split(",") if r]
     if "fp8_equal_recall" in rows and "fp32" in results:
         # FP8 + rerank at the FP32 form's recall: more bins (a bin's FP8 winner may be the
@@ -468,6 +533,7 @@ def main():
             log(" ", json.dumps(others[name_r]))
     if others:
         line["other_workloads"] = others
+    line["perf_model"] = perf_model_rows(line)
     if not args.no_cpu:
         threads = len(os.sched_getaffinity(0))
         log("cpu baseline: oracle on", threads, "threads")
