@@ -88,7 +88,11 @@ int64_t pick_bins_per_chunk(int64_t N, int64_t L, int64_t n_qb, int ng, int64_t 
   bpc = std::max(bpc, min_bpc);
   bpc = std::min(bpc, std::max(max_bpc, min_bpc));
   // whole 16-bin output windows of the distance kernel: item edges on window edges
-  if (bpc >= 16) bpc = bpc / 16 * 16;
+  // (or at least on 4-bin boundaries, which its 16-byte stores still cover)
+  if (bpc >= 16)
+    bpc = bpc / 16 * 16;
+  else if (bpc >= 4)
+    bpc = bpc / 4 * 4;
   return std::min<int64_t>(L, bpc);
 }
 

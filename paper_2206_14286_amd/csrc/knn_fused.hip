@@ -389,8 +389,9 @@ __device__ __forceinline__ void stage_bin(float* st, int qlocal, int bin, float 
 }
 
 // Write the window of bins [wb, wb + kWin) clipped to the item's bins [b0, b1) for the
-// wave's queries.  A full window goes out as 16-byte stores, four lanes per query
-// row (64 contiguous bytes each); a clipped one (item edges) bin by bin.
+// wave's queries.  With 16-byte aligned rows the window goes out as 16-byte stores,
+// four lanes per query row (64 contiguous bytes for a full window), four bins at a
+// time where the item's edge cuts it; otherwise bin by bin.
 template <int NCB>
 __device__ __forceinline__ void drain_window(const float* st, int wb, int b0, int b1, float* __restrict__ outV,
                                              int32_t* __restrict__ outA, int64_t ldo, int64_t wq0, int64_t M,
@@ -399,18 +400,29 @@ __device__ __forceinline__ void drain_window(const float* st, int wb, int b0, in
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int32_t* sa = reinterpret_cast<const int32_t*>(st) + 64 * kWinStride;
-  if (vec_ok && wb >= b0 && wb + kWin <= b1) {
+  if (vec_ok) {
+    // lane (query row ql, part) writes bins wb + 4 part .. + 3 of the row: one 16-byte
+    // store when all four are the item's, else the item's ones one by one
 #pragma unroll
     for (int s = 0; s < NCB * 32 / 16; ++s) {
       const int ql = 16 * s + (lane >> 2), part = lane & 3;
       const int64_t q = wq0 + ql;
+      const int pb = wb + 4 * part;
       const float* sv = st + ql * kWinStride + 4 * part;
       const int32_t* si = sa + ql * kWinStride + 4 * part;
-      const float4 v = make_float4(sv[0], sv[1], sv[2], sv[3]);
-      const int4 a = make_int4(si[0], si[1], si[2], si[3]);
       if (q < M) {
-        *reinterpret_cast<float4*>(outV + q * ldo + wb + 4 * part) = v;
-        *reinterpret_cast<int4*>(outA + q * ldo + wb + 4 * part) = a;
+        if (pb >= b0 && pb + 4 <= b1) {
+          *reinterpret_cast<float4*>(outV + q * ldo + pb) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+          *reinterpret_cast<int4*>(outA + q * ldo + pb) = make_int4(si[0], si[1], si[2], si[3]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (pb + e >= b0 && pb + e < b1) {
+              outV[q * ldo + pb + e] = sv[e];
+              outA[q * ldo + pb + e] = si[e];
+            }
+          }
+        }
       }
     }
   } else {
