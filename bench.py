@@ -210,10 +210,10 @@ def row_mips_small(torch, knn, datagen, reps=200):
             "us_per_call": sec * 1e6, "queries_per_s": M / sec, **kernel_frac(2.0 * M * N * 128, sec, "fp32")}
 
 
-def row_cosine_glove(torch, knn, datagen, oracle, steps, warmup, sample_n=32):
+def row_cosine_glove(torch, knn, datagen, oracle, steps, warmup, sample_n=256):
     """GloVe-shaped cosine search (K = 100, L = 16,384): FP32 plain against FP8 + FP32 rerank.
-    The FP8 form takes the first (L, rerank depth) of a short list that reaches the FP32
-    form's recall on the sample (more bins, then a deeper rerank)."""
+    The FP8 form takes the first (L, rerank depth) of a short list, in increasing cost,
+    that reaches the FP32 form's recall on the sample (a deeper rerank, more bins)."""
     w = datagen.WORKLOADS["cosine_glove"]
     Q, X = datagen.make("cosine_glove", seed=0)
     Qd, Xd = torch.from_numpy(Q).cuda(), torch.from_numpy(X).cuda()
@@ -236,7 +236,7 @@ def row_cosine_glove(torch, knn, datagen, oracle, steps, warmup, sample_n=32):
         db = knn.Database(Xd, "cosine", compute)
         rr, Lc = 0, L
         if compute == "fp8":
-            for Lc, rr in ((L, K), (L, 2 * K), (2 * L, K), (2 * L, 2 * K), (2 * L, 4 * K), (4 * L, 2 * K)):
+            for Lc, rr in ((L, 2 * K), (L, 4 * K), (2 * L, 2 * K), (2 * L, 4 * K), (4 * L, 2 * K), (4 * L, 4 * K)):
                 rec = recall_of(db.search(Qd[st], K, Lc, rerank=rr)[1].cpu().numpy())
                 log(f"  fp8 L={Lc} rerank {rr}: recall {rec:.4f}")
                 if rec >= out["fp32"]["recall_tie_aware"]:
