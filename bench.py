@@ -236,7 +236,11 @@ def row_cosine_glove(torch, knn, datagen, oracle, steps, warmup, sample_n=256):
         db = knn.Database(Xd, "cosine", compute)
         rr, Lc = 0, L
         if compute == "fp8":
-            for Lc, rr in ((L, 2 * K), (L, 4 * K), (2 * L, 2 * K), (2 * L, 4 * K), (4 * L, 2 * K), (4 * L, 4 * K)):
+            # more bins as bins of 2^W rows (Algorithm 1's ShiftRight form) where N allows:
+            # 64- and 32-row bins keep every bin boundary on a 32-row tile edge
+            more = [N // r if N % r == 0 else m * L for r, m in ((64, 2), (32, 4))]
+            for Lc, rr in ((L, 2 * K), (L, 4 * K), (more[0], 2 * K), (more[0], 4 * K), (more[1], 2 * K),
+                           (more[1], 4 * K)):
                 rec = recall_of(db.search(Qd[st], K, Lc, rerank=rr)[1].cpu().numpy())
                 log(f"  fp8 L={Lc} rerank {rr}: recall {rec:.4f}")
                 if rec >= out["fp32"]["recall_tie_aware"]:

@@ -389,49 +389,44 @@ __device__ __forceinline__ void stage_bin(float* st, int qlocal, int bin, float 
 }
 
 // Write the window of bins [wb, wb + kWin) clipped to the item's bins [b0, b1) for the
-// wave's queries.  With 16-byte aligned rows the window goes out as 16-byte stores,
-// four lanes per query row (64 contiguous bytes for a full window), four bins at a
-// time where the item's edge cuts it; otherwise bin by bin.
+// wave's queries.  Lane (query row ql, part) writes bins wb + 4 part .. + 3 of its row,
+// so each store instruction covers 64-byte segments of 16 rows: as one 16-byte store
+// when the row offsets allow it (vec = 4), as two 8-byte stores (vec = 2) or four
+// 4-byte ones (vec = 1); bins outside the item are skipped one by one.
 template <int NCB>
 __device__ __forceinline__ void drain_window(const float* st, int wb, int b0, int b1, float* __restrict__ outV,
                                              int32_t* __restrict__ outA, int64_t ldo, int64_t wq0, int64_t M,
-                                             bool vec_ok, int lane) {
+                                             int vec, int lane) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int32_t* sa = reinterpret_cast<const int32_t*>(st) + 64 * kWinStride;
-  if (vec_ok) {
-    // lane (query row ql, part) writes bins wb + 4 part .. + 3 of the row: one 16-byte
-    // store when all four are the item's, else the item's ones one by one
 #pragma unroll
-    for (int s = 0; s < NCB * 32 / 16; ++s) {
-      const int ql = 16 * s + (lane >> 2), part = lane & 3;
-      const int64_t q = wq0 + ql;
-      const int pb = wb + 4 * part;
-      const float* sv = st + ql * kWinStride + 4 * part;
-      const int32_t* si = sa + ql * kWinStride + 4 * part;
-      if (q < M) {
-        if (pb >= b0 && pb + 4 <= b1) {
-          *reinterpret_cast<float4*>(outV + q * ldo + pb) = make_float4(sv[0], sv[1], sv[2], sv[3]);
-          *reinterpret_cast<int4*>(outA + q * ldo + pb) = make_int4(si[0], si[1], si[2], si[3]);
-        } else {
+  for (int s = 0; s < NCB * 32 / 16; ++s) {
+    const int ql = 16 * s + (lane >> 2), part = lane & 3;
+    const int64_t q = wq0 + ql;
+    const int pb = wb + 4 * part;
+    const float* sv = st + ql * kWinStride + 4 * part;
+    const int32_t* si = sa + ql * kWinStride + 4 * part;
+    if (q < M) {
+      float* ov = outV + q * ldo + pb;
+      int32_t* oa = outA + q * ldo + pb;
+      if (pb >= b0 && pb + 4 <= b1 && vec == 4) {
+        *reinterpret_cast<float4*>(ov) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+        *reinterpret_cast<int4*>(oa) = make_int4(si[0], si[1], si[2], si[3]);
+      } else if (pb >= b0 && pb + 4 <= b1 && vec == 2) {
+        *reinterpret_cast<float2*>(ov) = make_float2(sv[0], sv[1]);
+        *reinterpret_cast<float2*>(ov + 2) = make_float2(sv[2], sv[3]);
+        *reinterpret_cast<int2*>(oa) = make_int2(si[0], si[1]);
+        *reinterpret_cast<int2*>(oa + 2) = make_int2(si[2], si[3]);
+      } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            if (pb + e >= b0 && pb + e < b1) {
-              outV[q * ldo + pb + e] = sv[e];
-              outA[q * ldo + pb + e] = si[e];
-            }
+        for (int e = 0; e < 4; ++e) {
+          if (pb + e >= b0 && pb + e < b1) {
+            ov[e] = sv[e];
+            oa[e] = si[e];
           }
         }
-      }
-    }
-  } else {
-    const int lo = wb > b0 ? wb : b0, hi = (wb + kWin) < b1 ? (wb + kWin) : b1;
-    const int64_t q = wq0 + lane;
-    if (lane < NCB * 32 && q < M) {
-      for (int b = lo; b < hi; ++b) {
-        outV[q * ldo + b] = st[lane * kWinStride + (b & (kWin - 1))];
-        outA[q * ldo + b] = sa[lane * kWinStride + (b & (kWin - 1))];
       }
     }
   }
@@ -481,8 +476,9 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int h = lane >> 5, ql = lane & 31;
   float* stage = reinterpret_cast<float*>(lds + S * G::kLdsBytes) + wave * kStageWords;
-  const bool vec_ok = ((reinterpret_cast<uintptr_t>(outV) | reinterpret_cast<uintptr_t>(outA)) & 15) == 0 &&
-                      (ldo & 3) == 0;
+  // widest store the output rows allow (window starts are multiples of 4 bins)
+  const uintptr_t oaddr = reinterpret_cast<uintptr_t>(outV) | reinterpret_cast<uintptr_t>(outA);
+  const int vec_ok = ((oaddr & 15) == 0 && (ldo & 3) == 0) ? 4 : (((oaddr & 7) == 0 && (ldo & 1) == 0) ? 2 : 1);
   const TileLoadPlan<NG> plan = make_load_plan<NG>(wave, lane);
 
   // rows and tiles fit in 32 bits (N < 2^31)
@@ -564,14 +560,34 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       bu[cb] = fast ? nbu[cb] : bu[cb];
     }
     auto flush_all = [&]() {  // the current bin is complete: stage it, open the next
+      if constexpr (NCB == 2) {
+        // lane half h stages column block h: it keeps its own half's state of block h
+        // and receives the other half's, in exchange for its state of block 1 - h
+        // (one exchange instead of one per block)
+        float kv = h ? bv[1] : bv[0], sv = h ? bv[0] : bv[1];
+        unsigned ku = h ? bu[1] : bu[0], su = h ? bu[0] : bu[1];
+        const unsigned off = 8u * (unsigned)h;  // group units: the half's first row
+        ku += (ku != kNoUnit && (ku & 1u)) ? off : 0u;
+        su += (su != kNoUnit && (su & 1u)) ? off : 0u;
+        const float ov = __shfl_xor(sv, 32);
+        const unsigned ou = __shfl_xor(su, 32);
+        const bool take = (ov > kv) || (ov == kv && ou < ku);
+        stage_bin(stage, h * 32 + ql, cur_bin, take ? ov : kv, take ? ou : ku, sign);
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        float mv;
-        unsigned mu;
-        merge_halves(bv[cb], bu[cb], h, mv, mu);
-        if (h == (cb & 1)) stage_bin(stage, cb * 32 + ql, cur_bin, mv, mu, sign);
-        bv[cb] = -INFINITY;
-        bu[cb] = kNoUnit;
+        for (int cb = 0; cb < NCB; ++cb) {
+          bv[cb] = -INFINITY;
+          bu[cb] = kNoUnit;
+        }
+      } else {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          float mv;
+          unsigned mu;
+          merge_halves(bv[cb], bu[cb], h, mv, mu);
+          if (h == (cb & 1)) stage_bin(stage, cb * 32 + ql, cur_bin, mv, mu, sign);
+          bv[cb] = -INFINITY;
+          bu[cb] = kNoUnit;
+        }
       }
       if ((cur_bin & (kWin - 1)) == kWin - 1 || cur_bin == b1 - 1)
         drain_window<NCB>(stage, cur_bin & ~(kWin - 1), (int)b0, (int)b1, outV, outA, ldo, wq0, M, vec_ok, lane);
@@ -585,10 +601,12 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     if (whole && cursor.peek2() >= t0 + 32) {
       // One bin boundary inside the tile, at row p (the bins on either side hold at
       // least the rest of the tile).  Groups of 4 rows that lie on one side update that
-      // side's bin as group units; only the group containing p (k* = p/8, when p is
-      // not a multiple of 4) is split, and it is folded in row by row with exact rows.
+      // side's bin as group units; only the group containing p (in group kb = p/8 of
+      // one lane half, when p is not a multiple of 4) is split, and it is folded in row
+      // by row with exact rows.
       const int p = (int)(cursor.next - t0);  // 1..31, uniform
-      const int kstar = (p & 3) ? (p >> 3) : -1;
+      const int kb = p >> 3;                   // groups k < kb: current bin; k > kb: next
+      const bool split = (p & 3) != 0;         // p inside a 4-row group (of group kb)
       const unsigned gbase = 2u * (unsigned)t0 + 8u * (unsigned)h;  // 2 * (first row of group 0)
       const int h4 = 4 * h;
 #pragma unroll
@@ -598,8 +616,19 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
         static_for<0, 4>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
           // the lane's group k holds tile rows 8k + 4h + j; row < p  <=>  4h < p - 8k - j
-          // (the right side is uniform: a compare against a scalar)
-          if (k == kstar) {
+          // (the right side is uniform: a compare against a scalar).  Groups other than
+          // kb lie on one side in both lane halves: a plain group update of that side.
+          if (k < kb) {
+            const float n = max5f(cv, acc_c[cb][4 * k], acc_c[cb][4 * k + 1], acc_c[cb][4 * k + 2],
+                                  acc_c[cb][4 * k + 3]);
+            cu = n > cv ? gu0 + 16u * k : cu;
+            cv = n;
+          } else if (k > kb) {
+            const float n = max5f(nv, acc_c[cb][4 * k], acc_c[cb][4 * k + 1], acc_c[cb][4 * k + 2],
+                                  acc_c[cb][4 * k + 3]);
+            nu = n > nv ? gu0 + 16u * k : nu;
+            nv = n;
+          } else if (split) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const float a = acc_c[cb][4 * k + j];
