@@ -1,7 +1,8 @@
 // knn_prepare.hip -- row preparation for the distance kernel.
 //
-// One thread per row (64-thread workgroups, loads batched 16 at a time so the
-// row is streamed rather than fetched element by element).  For cosine the row is unit-normalised in FP32 (|x|^2
+// One thread per row; a workgroup's 64 rows are first staged in LDS with coalesced
+// loads (the batched query segments read their rows directly).  For cosine the row is
+// unit-normalised in FP32 (|x|^2
 // summed in dimension order with one rounding per product and per sum, correctly
 // rounded square root and divisions), which makes cosine search an inner-product
 // search (Sec. 2: MIPS equals cosine search on l2-normalised data).  The row is
@@ -17,43 +18,44 @@ namespace knn {
 
 namespace {
 
-struct RowView {
+// Element d of a row in FP32 (0 past D or for a padding row), from global memory or
+// from a copy staged in LDS.
+struct GlobalRow {
   const void* src;
   int dt;
   int64_t base;
-  int D;
-  bool valid, cosine;
-  float nrm;
-  __device__ __forceinline__ float get(int d) const {
-    if (!valid || d >= D) return 0.f;
-    float x = load_elem(src, dt, base + d);
-    if (!cosine) return x;
-    return nrm > 0.f ? x / nrm : 0.f;  // correctly rounded division (HIP default)
-  }
+  __device__ __forceinline__ float operator()(int d) const { return load_elem(src, dt, base + d); }
+};
+struct LdsRow {
+  const float* row;
+  __device__ __forceinline__ float operator()(int d) const { return row[d]; }
 };
 
 // source row r (valid if r < rows) -> destination row dst of `tiles`
-template <int CDT>
-__device__ void prepare_row(const void* src, int in_dt, int64_t r, int64_t rows, int64_t dst, int D, int ng,
-                            int metric, bool database, unsigned char* tiles, float* orig_half_norm,
-                            float* orig_rnorm) {
+template <int CDT, class Src>
+__device__ void prepare_row(const Src& load, bool valid, int64_t r, int64_t dst, int D, int ng, int metric,
+                            bool database, unsigned char* tiles, float* orig_half_norm, float* orig_rnorm) {
   // one rounding per product and per sum: no fused multiply-add in this function
 #pragma clang fp contract(off)
-  const bool valid = src != nullptr && r < rows;
-  const int64_t base = r * (int64_t)D;
   float ss = 0.f;
   if (valid)
     for (int d0 = 0; d0 < D; d0 += 16) {  // 16 loads in flight, summed in dimension order
       float x[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = d0 + k < D ? load_elem(src, in_dt, base + d0 + k) : 0.f;
+      for (int k = 0; k < 16; ++k) x[k] = d0 + k < D ? load(d0 + k) : 0.f;
 #pragma unroll
       for (int k = 0; k < 16; ++k) ss = ss + x[k] * x[k];
     }
   const float nrm = sqrtf(ss);  // correctly rounded square root (HIP default)
   if (valid && orig_half_norm) orig_half_norm[r] = 0.5f * ss;
   if (valid && orig_rnorm) orig_rnorm[r] = nrm > 0.f ? 1.f / nrm : 0.f;
-  RowView v{src, in_dt, base, D, valid, metric == MET_COSINE, nrm};
+  const bool cosine = metric == MET_COSINE;
+  auto get = [&](int d) -> float {
+    if (!valid || d >= D) return 0.f;
+    const float x = load(d);
+    if (!cosine) return x;
+    return nrm > 0.f ? x / nrm : 0.f;  // correctly rounded division (HIP default)
+  };
 
   int e = 0;
   if (CDT == DT_FP8) {
@@ -61,7 +63,7 @@ __device__ void prepare_row(const void* src, int in_dt, int64_t r, int64_t rows,
     for (int d0 = 0; d0 < D; d0 += 16) {
       float x[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = v.get(d0 + k);
+      for (int k = 0; k < 16; ++k) x[k] = get(d0 + k);
 #pragma unroll
       for (int k = 0; k < 16; ++k) amax = fmaxf(amax, fabsf(x[k]));
     }
@@ -80,7 +82,7 @@ __device__ void prepare_row(const void* src, int in_dt, int64_t r, int64_t rows,
       u32x4 w = {0u, 0u, 0u, 0u};
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        float x = v.get(d0 + k);
+        float x = get(d0 + k);
         float deq;
         unsigned bits;
         if (CDT == DT_F32) {
@@ -107,14 +109,49 @@ __device__ void prepare_row(const void* src, int in_dt, int64_t r, int64_t rows,
   aux[128 + rr] = (unsigned char)(e + 127);
 }
 
+// The 64 rows of a workgroup are consecutive in the source, so they are first copied
+// into LDS with coalesced loads (consecutive threads, consecutive elements), widened to
+// FP32 (exact), one row per LDS row of D + 1 words (an odd stride: thread t reading
+// element d of its own row hits bank (t (D + 1) + d) mod 64, a different bank per
+// thread).  Each thread then prepares its own row from LDS with the arithmetic above.
+constexpr int kPrepRows = 64;
+
 template <int CDT>
-__global__ __launch_bounds__(64) void prepare_kernel(const void* src, int in_dt, int64_t rows, int D, int ng,
-                                                      int metric, int database, unsigned char* tiles,
-                                                      int64_t n_rows_padded, float* orig_half_norm,
-                                                      float* orig_rnorm) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kPrepRows) void prepare_kernel(const void* src, int in_dt, int64_t rows, int D, int ng,
+                                                             int metric, int database, unsigned char* tiles,
+                                                             int64_t n_rows_padded, float* orig_half_norm,
+                                                             float* orig_rnorm) {
+  extern __shared__ float stage[];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * kPrepRows;
+  const int64_t nrow = rows - r0 < kPrepRows ? (rows - r0 > 0 ? rows - r0 : 0) : kPrepRows;  // source rows here
+  const int total = (int)nrow * D;  // <= 64 * 256
+  const int64_t base = r0 * (int64_t)D;
+  // row of staged element i: floor((i + 1/2) / D) in FP32 is exact here, since (i + 1/2) / D
+  // is at least 1/(2D) away from an integer and i < 2^14
+  const float inv_d = 1.f / (float)D;
+  constexpr int U = 8;
+  for (int i0 = 0; i0 < total; i0 += kPrepRows * U) {
+    float x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kPrepRows + t;
+      x[u] = i < total ? load_elem(src, in_dt, base + i) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kPrepRows + t;
+      if (i < total) {
+        const int rr = (int)(((float)i + 0.5f) * inv_d), d = i - rr * D;
+        stage[rr * (D + 1) + d] = x[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t r = r0 + t;
   if (r >= n_rows_padded) return;
-  prepare_row<CDT>(src, in_dt, r, rows, r, D, ng, metric, database != 0, tiles, orig_half_norm, orig_rnorm);
+  prepare_row<CDT>(LdsRow{stage + t * (D + 1)}, src != nullptr && r < rows, r, r, D, ng, metric, database != 0,
+                   tiles, orig_half_norm, orig_rnorm);
 }
 
 template <int CDT>
@@ -129,8 +166,8 @@ __global__ __launch_bounds__(64) void prepare_segments_kernel(const QSeg* segs, 
   }
   const QSeg& s = segs[lo];
   const int64_t local = r - s.first;  // rows past s.rows are padding
-  prepare_row<CDT>(s.src, in_dt, local, s.rows, s.dst_row0 + local, s.D, s.ng, s.metric, false, s.tiles, nullptr,
-                   nullptr);
+  prepare_row<CDT>(GlobalRow{s.src, in_dt, local * (int64_t)s.D}, s.src != nullptr && local < s.rows, local,
+                   s.dst_row0 + local, s.D, s.ng, s.metric, false, s.tiles, nullptr, nullptr);
 }
 
 }  // namespace
@@ -142,16 +179,27 @@ hipError_t launch_prepare(const void* src, int in_dt, int64_t rows, int D, int m
   const int ng = groups_for(dpad_for(D, compute), compute);
   const int64_t n = n_tiles * kTileRows;
   if (n == 0) return hipSuccess;
-  const unsigned grid = (unsigned)ceil_div(n, 64);
+  const unsigned grid = (unsigned)ceil_div(n, kPrepRows);
+  const size_t lds = sizeof(float) * kPrepRows * (size_t)(D + 1);  // <= 65,792 bytes (D <= 256)
+  static bool attr_set[3] = {false, false, false};
+  if (!attr_set[compute]) {
+    const void* fn = compute == DT_F32    ? reinterpret_cast<const void*>(&prepare_kernel<DT_F32>)
+                     : compute == DT_BF16 ? reinterpret_cast<const void*>(&prepare_kernel<DT_BF16>)
+                                          : reinterpret_cast<const void*>(&prepare_kernel<DT_FP8>);
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)(sizeof(float) * kPrepRows * (kMaxDpad + 1)));
+    if (e != hipSuccess) return e;
+    attr_set[compute] = true;
+  }
   if (compute == DT_F32)
-    prepare_kernel<DT_F32><<<grid, 64, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
-                                                orig_half_norm, orig_rnorm);
+    prepare_kernel<DT_F32><<<grid, kPrepRows, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+                                                        orig_half_norm, orig_rnorm);
   else if (compute == DT_BF16)
-    prepare_kernel<DT_BF16><<<grid, 64, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
-                                                 orig_half_norm, orig_rnorm);
+    prepare_kernel<DT_BF16><<<grid, kPrepRows, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+                                                         orig_half_norm, orig_rnorm);
   else
-    prepare_kernel<DT_FP8><<<grid, 64, 0, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
-                                                orig_half_norm, orig_rnorm);
+    prepare_kernel<DT_FP8><<<grid, kPrepRows, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+                                                        orig_half_norm, orig_rnorm);
   return hipGetLastError();
 }
 
