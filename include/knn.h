@@ -113,7 +113,9 @@ knn_status knn_db_export(const knn_db* db, void* codes, int32_t* exponents, floa
 /* The plain FP32 search: Q (M x D) against X (N x D), both FP32 device arrays.
  * L <= 0 chooses L = knn_bins_for_recall(K, 0.95, N).  Writes the best K per query,
  * best first: out_val FP32[M x K], out_idx int32[M x K].  Allocates its temporary
- * buffers stream-ordered (hipMallocAsync) and prepares X on every call. */
+ * buffers stream-ordered and prepares X on every call.  Stream-ordered temporaries
+ * (here and in the other search calls) come from a memory pool the library creates
+ * per device, which keeps freed memory for later calls until the process ends. */
 knn_status knn_search(const float* Q, int64_t M, const float* X, int64_t N, int32_t D, int32_t K,
                       int64_t L, int32_t metric, float* out_val, int32_t* out_idx, void* stream);
 

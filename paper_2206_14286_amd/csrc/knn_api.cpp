@@ -104,12 +104,46 @@ int64_t bins_for_l2(int64_t N, int ng) {
   return std::max<int64_t>(1, std::min<int64_t>(l, N / kTileRows));
 }
 
-struct DevBuf {  // stream-ordered temporary
+// Stream-ordered temporaries come from a library-owned memory pool per device that
+// keeps freed blocks for reuse (release threshold: unlimited), so repeated searches do
+// not hand large temporaries back to the driver at every synchronisation and fetch
+// them again on the next call.
+hipError_t library_pool(hipMemPool_t* out) {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = pools.find(dev);
+  if (it != pools.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  hipMemPoolProps props = {};
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t pool = nullptr;
+  e = hipMemPoolCreate(&pool, &props);
+  if (e != hipSuccess) return e;
+  uint64_t keep = UINT64_MAX;
+  e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  if (e != hipSuccess) return e;
+  pools[dev] = pool;
+  *out = pool;
+  return hipSuccess;
+}
+
+struct DevBuf {  // stream-ordered temporary from the library pool
   void* p = nullptr;
   hipStream_t s = nullptr;
   hipError_t alloc(size_t bytes, hipStream_t st) {
     s = st;
-    return hipMallocAsync(&p, std::max<size_t>(bytes, 256), st);
+    hipMemPool_t pool;
+    hipError_t e = library_pool(&pool);
+    if (e != hipSuccess) return e;
+    return hipMallocFromPoolAsync(&p, std::max<size_t>(bytes, 256), pool, st);
   }
   ~DevBuf() {
     if (p) (void)hipFreeAsync(p, s);
