@@ -174,24 +174,198 @@ __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int
   __syncthreads();
 }
 
+// Rows of many candidates: the K-th best key is found from a histogram over the row's
+// own key range instead of byte by byte.  Pass 1: the smallest and largest key of the
+// row.  Pass 2: a kRangeBuckets-bucket histogram of (key - kmin) >> shift, shift the
+// smallest that fits the range into the buckets; the bucket b* holding the K-th best is
+// found by a scan from the top.  Pass 3: candidates in buckets above b* are winners;
+// those in b* are collected in LDS and sorted by (key, lower index first), and the best
+// of them complete the K.  Three reads of the row instead of five or more; when b*
+// holds more than kRangeCap candidates (a dense cluster of equal-looking scores) the
+// row falls back to the byte-wise radix select.
+constexpr int kRangeBuckets = 2048;
+constexpr int kRangeCap = 2048;
+
+struct RangeShared {
+  unsigned hist[kRangeBuckets];
+  unsigned long long bnd[kRangeCap];
+  unsigned kmin_w[kSelThreads / 64], kmax_w[kSelThreads / 64];
+  int bstar, above, nb, nhi;
+};
+
+union SelUnion {
+  SelShared radix;
+  struct {
+    unsigned long long keys[kMaxK];
+    RangeShared r;
+  } range;
+};
+
+__device__ __forceinline__ void bitonic_desc_lds(unsigned long long* a, int m) {
+  // m a power of two; all threads of the block take part
+  for (int size = 2; size <= m; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < m; i += kSelThreads) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;
+          const unsigned long long x = a[i], y = a[j];
+          if (desc ? (x < y) : (x > y)) {
+            a[i] = y;
+            a[j] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// f(c, key) for every candidate c of the row, the keys of kSelThreads * 8 candidates
+// loaded before any is used (enough bytes in flight to stream the row)
+template <class F>
+__device__ __forceinline__ void for_each_key(const float* __restrict__ V, int64_t n, int64_t es, float sgn, F f) {
+  constexpr int U = 8;
+  for (int64_t c0 = threadIdx.x; c0 < n; c0 += (int64_t)kSelThreads * U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t c = c0 + (int64_t)u * kSelThreads;
+      v[u] = c < n ? V[c * es] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t c = c0 + (int64_t)u * kSelThreads;
+      if (c < n) f(c, float_key(sgn * v[u] + 0.f));
+    }
+  }
+}
+
+__device__ void select_row_any(SelUnion& u, const float* __restrict__ V, const int32_t* __restrict__ A, int64_t n,
+                               int64_t es, int K, bool minimize, float* __restrict__ out_val,
+                               int32_t* __restrict__ out_idx, int64_t eo) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (K > n) K = (int)n;
+  const float sgn = minimize ? -1.f : 1.f;
+  RangeShared& r = u.range.r;
+  unsigned long long* keys = u.range.keys;
+  // pass 1: key range
+  unsigned lo = 0xFFFFFFFFu, hi = 0u;
+  for_each_key(V, n, es, sgn, [&](int64_t, unsigned k) {
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+  });
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned ol = (unsigned)__shfl_xor((int)lo, off), oh = (unsigned)__shfl_xor((int)hi, off);
+    lo = ol < lo ? ol : lo;
+    hi = oh > hi ? oh : hi;
+  }
+  if (lane == 0) {
+    r.kmin_w[w] = lo;
+    r.kmax_w[w] = hi;
+  }
+  for (int i = tid; i < kRangeBuckets; i += kSelThreads) r.hist[i] = 0;
+  __syncthreads();
+  unsigned kmin = r.kmin_w[0], kmax = r.kmax_w[0];
+#pragma unroll
+  for (int i = 1; i < kSelThreads / 64; ++i) {
+    kmin = r.kmin_w[i] < kmin ? r.kmin_w[i] : kmin;
+    kmax = r.kmax_w[i] > kmax ? r.kmax_w[i] : kmax;
+  }
+  const unsigned span = kmax - kmin;
+  int shift = 0;
+  while ((span >> shift) >= (unsigned)kRangeBuckets) ++shift;
+  // pass 2: histogram over the range
+  for_each_key(V, n, es, sgn, [&](int64_t, unsigned k) { atomicAdd(&r.hist[(k - kmin) >> shift], 1u); });
+  __syncthreads();
+  if (tid < 64) {  // one wave: lane l sums buckets [B - 32(l+1), B - 32l), top first
+    constexpr int PER = kRangeBuckets / 64;
+    unsigned sum = 0;
+#pragma unroll 8
+    for (int j = 0; j < PER; ++j) sum += r.hist[kRangeBuckets - 1 - PER * lane - j];
+    unsigned incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned t = (unsigned)__shfl_up((int)incl, off);
+      if (lane >= off) incl += t;
+    }
+    const unsigned excl = incl - sum;
+    if (excl < (unsigned)K && (unsigned)K <= incl) {
+      unsigned acc = excl;
+      for (int j = 0; j < PER; ++j) {
+        const int b = kRangeBuckets - 1 - PER * lane - j;
+        const unsigned cnt = r.hist[b];
+        if (acc + cnt >= (unsigned)K) {
+          r.bstar = b;
+          r.above = (int)acc;
+          break;
+        }
+        acc += cnt;
+      }
+    }
+    if (lane == 0) {
+      r.nb = 0;
+      r.nhi = 0;
+    }
+  }
+  __syncthreads();
+  const int bstar = r.bstar, above = r.above;
+  if ((int)r.hist[bstar] > kRangeCap) {  // uniform: fall back to the byte-wise select
+    __syncthreads();
+    select_row(u.radix, V, A, n, es, K, minimize, out_val, out_idx, eo);
+    return;
+  }
+  // pass 3: winners above b*, the b* bucket into LDS
+  for_each_key(V, n, es, sgn, [&](int64_t c, unsigned k) {
+    const int b = (int)((k - kmin) >> shift);
+    if (b >= bstar) {
+      const unsigned long long key = ((unsigned long long)k << 32) | unit_lo(A[c * es]);
+      if (b > bstar)
+        keys[atomicAdd(&r.nhi, 1)] = key;
+      else
+        r.bnd[atomicAdd(&r.nb, 1)] = key;
+    }
+  });
+  __syncthreads();
+  const int nb = r.nb;
+  int mb = 1;
+  while (mb < nb) mb <<= 1;
+  for (int i = nb + tid; i < mb; i += kSelThreads) r.bnd[i] = 0ull;
+  __syncthreads();
+  bitonic_desc_lds(r.bnd, mb);
+  for (int i = tid; i < K - above; i += kSelThreads) keys[above + i] = r.bnd[i];
+  int kp = 1;
+  while (kp < K) kp <<= 1;
+  for (int i = K + tid; i < kp; i += kSelThreads) keys[i] = 0ull;
+  __syncthreads();
+  bitonic_desc_lds(keys, kp);
+  for (int i = tid; i < K; i += kSelThreads) {
+    const unsigned long long key = keys[i];
+    out_val[i * eo] = sgn * key_float((unsigned)(key >> 32));
+    out_idx[i * eo] = unit_code((unsigned)(key & 0xFFFFFFFFull));
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kSelThreads) void select_kernel(const float* __restrict__ V,
                                                              const int32_t* __restrict__ A, int64_t rows, int64_t n,
                                                              int64_t ldv, int64_t es, int K, int minimize,
                                                              float* __restrict__ out_val,
                                                              int32_t* __restrict__ out_idx, int64_t ldout,
                                                              int64_t eo) {
-  __shared__ SelShared sh;
+  __shared__ SelUnion sh;
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x)
-    select_row(sh, V + r * ldv, A + r * ldv, n, es, K, minimize != 0, out_val + r * ldout, out_idx + r * ldout,
-               eo);
+    select_row_any(sh, V + r * ldv, A + r * ldv, n, es, K, minimize != 0, out_val + r * ldout,
+                   out_idx + r * ldout, eo);
 }
 
 __global__ __launch_bounds__(kSelThreads) void select_rows_kernel(const SelRow* __restrict__ rows_desc,
                                                                   int64_t rows) {
-  __shared__ SelShared sh;
+  __shared__ SelUnion sh;
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
     const SelRow d = rows_desc[r];
-    select_row(sh, d.V, d.A, d.n, 1, d.K, d.minimize != 0, d.out_val, d.out_idx, 1);
+    select_row_any(sh, d.V, d.A, d.n, 1, d.K, d.minimize != 0, d.out_val, d.out_idx, 1);
   }
 }
 
