@@ -58,6 +58,11 @@ CASES = [
     ("cols_single_column", 5000, 1, 0, "fp32", 5, 5000, False, True, 0, "ints", -1),
     ("cols_masked", 3000, 70, 0, "fp32", 10, 40, False, True, 0, "masked", -1),
     ("cols_split_bins", 20000, 130, 0, "fp32", 10, 50, False, True, 0, "ints", -1),
+    # top-K over more than 1024 bin winners: the key-range select, its byte-wise fallback
+    # (thousands of equal winners in one bucket) and element strides (dimension 0)
+    ("rows_select_range_min", 4, 200000, 1, "fp32", 100, 5000, True, True, 0, "normal", -1),
+    ("rows_select_many_ties", 3, 300000, 1, "fp32", 10, 20000, False, True, 0, "ints", -1),
+    ("cols_select_strided", 60000, 16, 0, "fp32", 50, 3000, False, True, 0, "normal", -1),
     ("cols_split_bf16_min_strided", 9001, 65, 0, "bf16", 5, 7, True, False, 3, "ints", -1),
 ]
 
