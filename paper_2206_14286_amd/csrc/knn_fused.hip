@@ -839,12 +839,9 @@ hipError_t launch_one(const FusedParams& p, hipStream_t s) {
   const int64_t per_xcd = ceil_div(p.n_chunks, 8);
   const int64_t grid = 8 * per_xcd * p.n_qb;
   constexpr int lb = lds_bytes<DT, NG>();
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_kernel<DT, NG, NCB>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lb);
+  {
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&fused_kernel<DT, NG, NCB>), lb);
     if (e != hipSuccess) return e;
-    attr_set = true;
   }
   fused_kernel<DT, NG, NCB><<<dim3((unsigned)grid), dim3(64 * kWaves), lb, s>>>(p);
   return hipGetLastError();
@@ -936,12 +933,9 @@ hipError_t launch_fused_persistent(int dt, const GroupDesc* d_groups, const Work
   if (dt != DT_BF16) return hipErrorInvalidValue;  // the batched form is built for BF16 databases
   const int lb = lds_bytes_needed;
   (void)hipGetLastError();
-  static int attr_bytes = 0;
-  if (lb > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_persistent_kernel<DT_BF16>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lb);
+  {
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&fused_persistent_kernel<DT_BF16>), lb);
     if (e != hipSuccess) return e;
-    attr_bytes = lb;
   }
   fused_persistent_kernel<DT_BF16><<<n_blocks, 64 * kWaves, lb, s>>>(d_groups, d_items, n_items);
   return hipGetLastError();

@@ -18,6 +18,10 @@
 // Padding rows (beyond N or M) are zero with init 0 and scale byte 127.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
 #include <stdint.h>
 
 namespace knn {
@@ -105,6 +109,22 @@ struct GroupDesc {     // all queries against one database, concatenated
 // lds_bytes_needed: the largest fused_lds_bytes() over the groups the items touch
 hipError_t launch_fused_persistent(int dt, const GroupDesc* d_groups, const WorkItem* d_items, int64_t n_items,
                                    int n_blocks, int lds_bytes_needed, hipStream_t s);
+
+// Raise a kernel's dynamic LDS limit to at least `bytes` on the current device (once
+// per kernel, device and size; function attributes are per device).
+inline hipError_t ensure_dynamic_lds(const void* fn, int bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> granted;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  int& cur = granted[{fn, dev}];
+  if (cur >= bytes) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) cur = bytes;
+  return e;
+}
 
 // ---- exact top-K over candidate lists (ExactRescoring)
 // row r: candidates V[r*ldv + c], A[r*ldv + c] for c < n, in the metric's own sign.

@@ -181,15 +181,12 @@ hipError_t launch_prepare(const void* src, int in_dt, int64_t rows, int D, int m
   if (n == 0) return hipSuccess;
   const unsigned grid = (unsigned)ceil_div(n, kPrepRows);
   const size_t lds = sizeof(float) * kPrepRows * (size_t)(D + 1);  // <= 65,792 bytes (D <= 256)
-  static bool attr_set[3] = {false, false, false};
-  if (!attr_set[compute]) {
+  {
     const void* fn = compute == DT_F32    ? reinterpret_cast<const void*>(&prepare_kernel<DT_F32>)
                      : compute == DT_BF16 ? reinterpret_cast<const void*>(&prepare_kernel<DT_BF16>)
                                           : reinterpret_cast<const void*>(&prepare_kernel<DT_FP8>);
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)(sizeof(float) * kPrepRows * (kMaxDpad + 1)));
+    const hipError_t e = ensure_dynamic_lds(fn, (int)lds);
     if (e != hipSuccess) return e;
-    attr_set[compute] = true;
   }
   if (compute == DT_F32)
     prepare_kernel<DT_F32><<<grid, kPrepRows, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
