@@ -357,12 +357,13 @@ __device__ __forceinline__ void mma_tile_chunked(f32x16 (&acc)[NCB], const unsig
 // take it from a scalar; merge_halves adds the offset back.
 constexpr unsigned kNoUnit = 0xFFFFFFFFu;
 
-// max(best, a0..a3) nested so that the compiler's max3 matching (outermost first)
-// yields two v_max3_f32: max3(best, a3, max3(a0, a1, a2)).  Plain code rather than
-// asm, so that the compiler also inserts the wait states that reading a matrix
-// instruction's fresh result needs.
+// max(best, a0..a3) folded left to right, which the compiler turns into two v_max3_f32:
+// max3(max3(best, a0, a1), a2, a3).  (Nested the other way, it computes the group's
+// own maximum first and spends a third instruction on the running best.)  Plain code
+// rather than asm, so that the compiler also inserts the wait states that reading a
+// matrix instruction's fresh result needs.
 __device__ __forceinline__ float max5f(float best, float a0, float a1, float a2, float a3) {
-  return fmaxf(best, fmaxf(a3, fmaxf(a0, fmaxf(a1, a2))));
+  return fmaxf(fmaxf(fmaxf(fmaxf(best, a0), a1), a2), a3);
 }
 
 // merge the two lane halves' (value, unit) of one query: larger value, then lower unit
@@ -642,16 +643,21 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
               nu = c2 ? code : nu;
             }
           } else {
-            const float g = fmaxf(fmaxf(fmaxf(acc_c[cb][4 * k], acc_c[cb][4 * k + 1]), acc_c[cb][4 * k + 2]),
-                                  acc_c[cb][4 * k + 3]);
+            // p a multiple of 4: group kb lies on one side in each lane half.  Written
+            // with max5f like the fast path's update, so that the only subexpression the
+            // compiler can share with it is max3(a0, a1, a2), which costs the fast path
+            // nothing (a shared full group maximum would cost it one more instruction).
             const bool in_cur = h4 < p - 8 * k;  // the whole group is on one side
             const unsigned code = gu0 + 16u * k;  // lane-local group unit
-            const float gc = in_cur ? g : -INFINITY, gn = in_cur ? -INFINITY : g;
-            const bool c1 = gc > cv, c2 = gn > nv;
-            cv = c1 ? gc : cv;
+            const float n1 = max5f(cv, acc_c[cb][4 * k], acc_c[cb][4 * k + 1], acc_c[cb][4 * k + 2],
+                                   acc_c[cb][4 * k + 3]);
+            const float n2 = max5f(nv, acc_c[cb][4 * k], acc_c[cb][4 * k + 1], acc_c[cb][4 * k + 2],
+                                   acc_c[cb][4 * k + 3]);
+            const bool c1 = in_cur && n1 > cv, c2 = !in_cur && n2 > nv;
             cu = c1 ? code : cu;
-            nv = c2 ? gn : nv;
+            cv = in_cur ? n1 : cv;
             nu = c2 ? code : nu;
+            nv = in_cur ? nv : n2;
           }
         });
         bv[cb] = cv;
