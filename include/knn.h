@@ -28,7 +28,7 @@
  *   - Arguments are checked before anything is enqueued.  On error the call returns
  *     a non-zero knn_status, knn_last_error() describes it (per thread), nothing is
  *     enqueued and the outputs are untouched.  No C++ exception crosses the ABI.
- *   - Sizes: 1 <= K <= L <= N < 2^31, 1 <= D <= 256, M >= 0 (M = 0 is a no-op).
+ *   - Sizes: 1 <= K <= L <= N <= 2^31 - 64, 1 <= D <= 256, M >= 0 (M = 0 is a no-op).
  *     Row indices are int32.
  *   - Inputs with NaN or infinity give unspecified results (they are not scanned).
  */

@@ -52,7 +52,9 @@ bool valid_compute(int32_t t) { return t == KNN_F32 || t == KNN_BF16 || t == KNN
 
 knn_status check_sizes(int64_t M, int64_t N, int32_t D, int32_t K, int64_t L) {
   if (M < 0) return fail(KNN_ERR_INVALID, "M must be >= 0 (got %lld)", (long long)M);
-  if (N < 1 || N >= (int64_t(1) << 31)) return fail(KNN_ERR_INVALID, "N must be in [1, 2^31) (got %lld)", (long long)N);
+  // rows of a 32-row tile plus 32 stay below 2^31 in the distance kernel's 32-bit row arithmetic
+  if (N < 1 || N > kMaxRows)
+    return fail(KNN_ERR_INVALID, "N must be in [1, 2^31 - 64] (got %lld)", (long long)N);
   if (D < 1) return fail(KNN_ERR_INVALID, "D must be >= 1 (got %d)", D);
   if (D > kMaxDpad) return fail(KNN_ERR_UNSUPPORTED, "D must be <= %d (got %d)", kMaxDpad, D);
   if (K < 1 || K > 1024) return fail(KNN_ERR_INVALID, "K must be in [1, 1024] (got %d)", K);
@@ -238,7 +240,7 @@ extern "C" knn_status knn_db_create(const void* X, int32_t in_dtype, int64_t N, 
   if (!valid_in(in_dtype)) return fail(KNN_ERR_INVALID, "in_dtype must be KNN_F32 or KNN_BF16");
   if (!valid_compute(compute)) return fail(KNN_ERR_INVALID, "bad compute dtype %d", compute);
   if (!valid_metric(metric)) return fail(KNN_ERR_INVALID, "bad metric %d", metric);
-  if (N < 1 || N >= (int64_t(1) << 31)) return fail(KNN_ERR_INVALID, "N must be in [1, 2^31)");
+  if (N < 1 || N > kMaxRows) return fail(KNN_ERR_INVALID, "N must be in [1, 2^31 - 64]");
   if (D < 1) return fail(KNN_ERR_INVALID, "D must be >= 1");
   if (D > kMaxDpad) return fail(KNN_ERR_UNSUPPORTED, "D must be <= %d", kMaxDpad);
   hipStream_t s = (hipStream_t)stream;
@@ -493,7 +495,7 @@ extern "C" knn_status knn_backward(const float* g, const int32_t* idx, const voi
                                    int32_t in_dtype, int64_t M, int64_t N, int32_t D, int32_t K, int32_t metric,
                                    float* dQ, float* dX, void* stream) {
   g_last_error.clear();
-  if (M < 0 || N < 1 || N >= (int64_t(1) << 31) || D < 1 || K < 1)
+  if (M < 0 || N < 1 || N > kMaxRows || D < 1 || K < 1)
     return fail(KNN_ERR_INVALID, "bad sizes (M=%lld N=%lld D=%d K=%d)", (long long)M, (long long)N, D, K);
   if (D > kMaxDpad) return fail(KNN_ERR_UNSUPPORTED, "D must be <= %d", kMaxDpad);
   if (!valid_in(in_dtype)) return fail(KNN_ERR_INVALID, "in_dtype must be KNN_F32 or KNN_BF16");
@@ -530,8 +532,8 @@ extern "C" knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_
   if (minimize != 0 && minimize != 1) return fail(KNN_ERR_INVALID, "minimize must be 0 or 1");
   if (aggregate_to_topk != 0 && aggregate_to_topk != 1) return fail(KNN_ERR_INVALID, "aggregate_to_topk must be 0 or 1");
   const int64_t n = reduction_dim == 1 ? cols : rows, B = reduction_dim == 1 ? rows : cols;
-  if (n < 1 || n >= (int64_t(1) << 31))
-    return fail(KNN_ERR_INVALID, "the reduced dimension must have 1 .. 2^31 - 1 entries (got %lld)", (long long)n);
+  if (n < 1 || n > kMaxRows)
+    return fail(KNN_ERR_INVALID, "the reduced dimension must have 1 .. 2^31 - 64 entries (got %lld)", (long long)n);
   if (K < 1 || K > n) return fail(KNN_ERR_INVALID, "need 1 <= K <= reduced size (K=%d, n=%lld)", K, (long long)n);
   if (aggregate_to_topk && K > 1024) return fail(KNN_ERR_INVALID, "K must be <= 1024 (got %d)", K);
   if (L <= 0) {

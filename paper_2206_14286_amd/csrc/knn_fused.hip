@@ -439,8 +439,11 @@ __device__ __forceinline__ void drain_window(const float* st, int wb, int b0, in
 
 // Walks the first rows floor(b N / L) of consecutive bins without dividing:
 // `next` is the first row of the bin after the current one, rem = (b+1) N mod L.
+// next32 is `next` clamped to 2^31 - 1, for the per-tile compares against rows
+// t0 + 32 <= N + 31 < 2^31 (32-bit scalar compares instead of 64-bit vector ones).
 struct BinCursor {
   int64_t next;
+  int next32;
   unsigned rem, nr, L;  // rem, N mod L, L (all < 2^31)
   int64_t nq;           // N / L
   __device__ __forceinline__ int64_t peek2() const { return next + nq + (rem + nr >= L ? 1 : 0); }
@@ -448,6 +451,7 @@ struct BinCursor {
     const unsigned r = rem + nr;
     const bool c = r >= L;
     next += nq + (c ? 1 : 0);
+    next32 = next < 0x7FFFFFFF ? (int)next : 0x7FFFFFFF;
     rem = c ? r - L : r;
   }
 };
@@ -455,6 +459,7 @@ struct BinCursor {
 __device__ __forceinline__ BinCursor make_cursor(int64_t b, int64_t N, int64_t L) {
   BinCursor c;
   c.next = bin_start(b + 1, N, L);
+  c.next32 = c.next < 0x7FFFFFFF ? (int)c.next : 0x7FFFFFFF;
   c.rem = (unsigned)(((b + 1) * N) % L);
   c.nr = (unsigned)(N % L);
   c.L = (unsigned)L;
@@ -550,7 +555,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     const int lo = t0 > r0 ? t0 : r0;
     const int hi = (t0 + 32) < r1 ? (t0 + 32) : r1;
     const bool whole = lo == t0 && hi == t0 + 32;  // the tile lies inside the item's rows
-    const bool fast = whole && t0 + 32 <= cursor.next;  // whole tile in the current bin
+    const bool fast = whole && t0 + 32 <= cursor.next32;  // whole tile in the current bin
     float obv[NCB];
     unsigned obu[NCB];
 #pragma unroll
@@ -596,7 +601,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       cursor.advance();
     };
     if (fast) {
-      if (t0 + 32 == cursor.next) flush_all();  // the bin ends with this tile
+      if (t0 + 32 == cursor.next32) flush_all();  // the bin ends with this tile
       return;
     }
     if (whole && cursor.peek2() >= t0 + 32) {
@@ -605,7 +610,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       // side's bin as group units; only the group containing p (in group kb = p/8 of
       // one lane half, when p is not a multiple of 4) is split, and it is folded in row
       // by row with exact rows.
-      const int p = (int)(cursor.next - t0);  // 1..31, uniform
+      const int p = cursor.next32 - t0;  // 1..31, uniform
       const int kb = p >> 3;                   // groups k < kb: current bin; k > kb: next
       const bool split = (p & 3) != 0;         // p inside a 4-row group (of group kb)
       const unsigned gbase = 2u * (unsigned)t0 + 8u * (unsigned)h;  // 2 * (first row of group 0)
@@ -671,7 +676,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
         bv[cb] = obv[cb];
         bu[cb] = obu[cb];
       }
-      if (t0 + 32 == cursor.next) flush_all();  // the next bin ends with the tile too
+      if (t0 + 32 == cursor.next32) flush_all();  // the next bin ends with the tile too
       return;
     }
     // The tile crosses the item's edge or holds several bin boundaries: walk its rows
@@ -708,7 +713,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     };
     for (int jj = lo - t0; jj < hi - t0; ++jj) {  // uniform bounds
       const int j = t0 + jj;
-      if (j == cursor.next) flush_row();
+      if (j == cursor.next32) flush_row();
       const int ir = 4 * (jj >> 3) + (jj & 3), hr = (jj >> 2) & 1;  // accumulator and lane half of row jj
       const float a = acc_c[0][ir], b = acc_c[cB][ir];
       const float other = __shfl_xor(h == 0 ? b : a, 32);
@@ -718,7 +723,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
         su = 2u * (unsigned)j;
       }
     }
-    if (hi == cursor.next) flush_row();
+    if (hi == cursor.next32) flush_row();
     // back to the per-half form: half 0 carries the open bin's state
     {
       const float vA = __shfl(sv, ql);

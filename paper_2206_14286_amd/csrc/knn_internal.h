@@ -33,6 +33,9 @@ constexpr int kTileRows = 32;
 constexpr int kAuxBytes = 256;
 constexpr int kWaves = 4;             // waves per workgroup of the distance kernel
 constexpr int kMaxDpad = 256;
+// most rows of a database (or scores along a reduced dimension): the kernels do row
+// arithmetic in 32 bits and look up to a 32-row tile (or a 32-score lane chunk) ahead
+constexpr int64_t kMaxRows = (int64_t(1) << 31) - 64;
 
 __host__ __device__ inline int elem_bytes(int dt) { return dt == DT_F32 ? 4 : (dt == DT_BF16 ? 2 : 1); }
 // padded depth: a multiple of one fragment group pair (32 bytes per row) and of the MFMA K step
