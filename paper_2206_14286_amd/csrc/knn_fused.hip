@@ -607,12 +607,12 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     if (whole && cursor.peek2() >= t0 + 32) {
       // One bin boundary inside the tile, at row p (the bins on either side hold at
       // least the rest of the tile).  Groups of 4 rows that lie on one side update that
-      // side's bin as group units; only the group containing p (in group kb = p/8 of
-      // one lane half, when p is not a multiple of 4) is split, and it is folded in row
-      // by row with exact rows.
+      // side's bin as group units (masked, in straight-line code: branching per group
+      // costs registers that the persistent kernel, which holds every depth's code,
+      // does not have); only the group containing p (k* = p/8, when p is not a
+      // multiple of 4) is split, and it is folded in row by row with exact rows.
       const int p = cursor.next32 - t0;  // 1..31, uniform
-      const int kb = p >> 3;                   // groups k < kb: current bin; k > kb: next
-      const bool split = (p & 3) != 0;         // p inside a 4-row group (of group kb)
+      const int kstar = (p & 3) ? (p >> 3) : -1;
       const unsigned gbase = 2u * (unsigned)t0 + 8u * (unsigned)h;  // 2 * (first row of group 0)
       const int h4 = 4 * h;
 #pragma unroll
@@ -622,19 +622,8 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
         static_for<0, 4>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
           // the lane's group k holds tile rows 8k + 4h + j; row < p  <=>  4h < p - 8k - j
-          // (the right side is uniform: a compare against a scalar).  Groups other than
-          // kb lie on one side in both lane halves: a plain group update of that side.
-          if (k < kb) {
-            const float n = max5f(cv, acc_c[cb][4 * k], acc_c[cb][4 * k + 1], acc_c[cb][4 * k + 2],
-                                  acc_c[cb][4 * k + 3]);
-            cu = n > cv ? gu0 + 16u * k : cu;
-            cv = n;
-          } else if (k > kb) {
-            const float n = max5f(nv, acc_c[cb][4 * k], acc_c[cb][4 * k + 1], acc_c[cb][4 * k + 2],
-                                  acc_c[cb][4 * k + 3]);
-            nu = n > nv ? gu0 + 16u * k : nu;
-            nv = n;
-          } else if (split) {
+          // (the right side is uniform: a compare against a scalar)
+          if (k == kstar) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
               const float a = acc_c[cb][4 * k + j];
@@ -648,21 +637,16 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
               nu = c2 ? code : nu;
             }
           } else {
-            // p a multiple of 4: group kb lies on one side in each lane half.  Written
-            // with max5f like the fast path's update, so that the only subexpression the
-            // compiler can share with it is max3(a0, a1, a2), which costs the fast path
-            // nothing (a shared full group maximum would cost it one more instruction).
+            const float g = fmaxf(fmaxf(fmaxf(acc_c[cb][4 * k], acc_c[cb][4 * k + 1]), acc_c[cb][4 * k + 2]),
+                                  acc_c[cb][4 * k + 3]);
             const bool in_cur = h4 < p - 8 * k;  // the whole group is on one side
             const unsigned code = gu0 + 16u * k;  // lane-local group unit
-            const float n1 = max5f(cv, acc_c[cb][4 * k], acc_c[cb][4 * k + 1], acc_c[cb][4 * k + 2],
-                                   acc_c[cb][4 * k + 3]);
-            const float n2 = max5f(nv, acc_c[cb][4 * k], acc_c[cb][4 * k + 1], acc_c[cb][4 * k + 2],
-                                   acc_c[cb][4 * k + 3]);
-            const bool c1 = in_cur && n1 > cv, c2 = !in_cur && n2 > nv;
+            const float gc = in_cur ? g : -INFINITY, gn = in_cur ? -INFINITY : g;
+            const bool c1 = gc > cv, c2 = gn > nv;
+            cv = c1 ? gc : cv;
             cu = c1 ? code : cu;
-            cv = in_cur ? n1 : cv;
+            nv = c2 ? gn : nv;
             nu = c2 ? code : nu;
-            nv = in_cur ? nv : n2;
           }
         });
         bv[cb] = cv;
