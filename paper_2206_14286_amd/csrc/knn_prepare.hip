@@ -124,26 +124,58 @@ __global__ __launch_bounds__(kPrepRows) void prepare_kernel(const void* src, int
   extern __shared__ float stage[];
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * kPrepRows;
-  const int64_t nrow = rows - r0 < kPrepRows ? (rows - r0 > 0 ? rows - r0 : 0) : kPrepRows;  // source rows here
+  const int64_t nrow = src == nullptr ? 0 : (rows - r0 < kPrepRows ? (rows - r0 > 0 ? rows - r0 : 0) : kPrepRows);
   const int total = (int)nrow * D;  // <= 64 * 256
   const int64_t base = r0 * (int64_t)D;
   // row of staged element i: floor((i + 1/2) / D) in FP32 is exact here, since (i + 1/2) / D
   // is at least 1/(2D) away from an integer and i < 2^14
   const float inv_d = 1.f / (float)D;
-  constexpr int U = 8;
-  for (int i0 = 0; i0 < total; i0 += kPrepRows * U) {
-    float x[U];
+  auto put = [&](int i, float x) {
+    const int rr = (int)(((float)i + 0.5f) * inv_d), d = i - rr * D;
+    stage[rr * (D + 1) + d] = x;
+  };
+  const int esz = in_dt == DT_F32 ? 4 : 2;
+  if (reinterpret_cast<uintptr_t>(src) % 16 == 0 && (D * esz) % 16 == 0) {
+    // 16-byte loads (the block's rows are one aligned span): 8 per thread in flight
+    const int per = 16 / esz, total16 = total / per;
+    const u32x4* s16 = reinterpret_cast<const u32x4*>(static_cast<const unsigned char*>(src) + base * esz);
+    constexpr int U = 8;
+    for (int i0 = 0; i0 < total16; i0 += kPrepRows * U) {
+      u32x4 w[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * kPrepRows + t;
-      x[u] = i < total ? load_elem(src, in_dt, base + i) : 0.f;
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kPrepRows + t;
+        w[u] = i < total16 ? s16[i] : u32x4{0u, 0u, 0u, 0u};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kPrepRows + t;
+        if (i >= total16) continue;
+        if (in_dt == DT_F32) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) put(i * 4 + k, __uint_as_float(w[u][k]));
+        } else {
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const unsigned h = (k & 1) ? (w[u][k >> 1] >> 16) : (w[u][k >> 1] & 0xFFFFu);
+            put(i * 8 + k, __uint_as_float(h << 16));
+          }
+        }
+      }
     }
+  } else {
+    constexpr int U = 8;
+    for (int i0 = 0; i0 < total; i0 += kPrepRows * U) {
+      float x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * kPrepRows + t;
-      if (i < total) {
-        const int rr = (int)(((float)i + 0.5f) * inv_d), d = i - rr * D;
-        stage[rr * (D + 1) + d] = x[u];
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kPrepRows + t;
+        x[u] = i < total ? load_elem(src, in_dt, base + i) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kPrepRows + t;
+        if (i < total) put(i, x[u]);
       }
     }
   }
