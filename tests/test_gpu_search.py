@@ -64,6 +64,13 @@ CASES = [
     ("cosine", 64, 4100, 128, 10, 120, "fp32"),    # bins of 34-35 rows, ragged tail tile
     ("mips", 300, 3000, 192, 10, 50, "bf16"),      # depth 192: the single-accumulator form
     ("l2", 200, 2500, 256, 10, 40, "bf16"),        # depth 256, L2, bins of 62-63 rows
+    # every remaining (compute type, depth, column blocks) kernel instance
+    ("mips", 150, 2000, 192, 10, 70, "fp8"),       # FP8 depth 192: double-buffered form
+    ("l2", 260, 3000, 256, 10, 90, "fp8"),         # FP8 depth 256: single-accumulator form
+    ("cosine", 90, 2000, 250, 5, 64, "fp8"),       # FP8 depth 256, one column block
+    ("mips", 140, 1800, 192, 8, 55, "fp32"),       # FP32 depth 192
+    ("l2", 300, 2000, 20, 10, 100, "bf16"),        # BF16 depth 32
+    ("mips", 100, 2222, 128, 10, 70, "bf16"),      # BF16 depth 128, one column block
 ]
 
 
