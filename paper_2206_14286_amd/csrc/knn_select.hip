@@ -401,6 +401,62 @@ __global__ __launch_bounds__(256) void select_wave_kernel(const float* __restric
   }
 }
 
+// Few results from short rows (K <= 32, n <= 64 R): each lane sorts its R keys, then K
+// rounds take the wave's best remaining key (a butterfly maximum over the lanes' heads)
+// and the lane holding it drops its head.  About half the instructions of sorting all
+// 64 R keys when K is small.  Same order as the other paths.
+template <int R>
+__global__ __launch_bounds__(256) void select_wave_few_kernel(const float* __restrict__ V,
+                                                              const int32_t* __restrict__ A, int64_t rows, int n,
+                                                              int64_t ldv, int64_t es, int K, int minimize,
+                                                              float* __restrict__ out_val,
+                                                              int32_t* __restrict__ out_idx, int64_t ldout,
+                                                              int64_t eo) {
+  const int lane = threadIdx.x & 63;
+  const float sgn = minimize ? -1.f : 1.f;
+  if (K > n) K = n;
+  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < rows; r += (int64_t)gridDim.x * 4) {
+    unsigned long long k[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int c = 64 * i + lane;
+      k[i] = c < n ? (((unsigned long long)float_key(sgn * V[r * ldv + c * es] + 0.f) << 32) |
+                      unit_lo(A[r * ldv + c * es]))
+                   : 0ull;
+    }
+    // sort the lane's keys, largest first (insertion network over R registers)
+#pragma unroll
+    for (int i = 1; i < R; ++i) {
+#pragma unroll
+      for (int j = i; j > 0; --j) {
+        const unsigned long long a = k[j - 1], b = k[j];
+        k[j - 1] = a > b ? a : b;
+        k[j] = a > b ? b : a;
+      }
+    }
+    for (int e = 0; e < K; ++e) {
+      unsigned long long m = k[0];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = shfl_xor_u64(m, off);
+        m = o > m ? o : m;
+      }
+      // the lowest lane whose head is the maximum pops it (keys of real candidates are
+      // unique; empty slots are all 0 and are never taken before real ones)
+      const unsigned long long holders = __ballot(k[0] == m);
+      if (lane == __ffsll((long long)holders) - 1) {
+#pragma unroll
+        for (int i = 0; i + 1 < R; ++i) k[i] = k[i + 1];
+        k[R - 1] = 0ull;
+      }
+      if (lane == 0) {
+        out_val[r * ldout + e * eo] = sgn * key_float((unsigned)(m >> 32));
+        out_idx[r * ldout + e * eo] = unit_code((unsigned)(m & 0xFFFFFFFFull));
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t n, int64_t ldv, int K,
@@ -413,8 +469,14 @@ hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t
     const int64_t want = ceil_div(rows, 4);
     const unsigned grid = (unsigned)(want < 65536 ? want : 65536);
     const int nn = (int)n, mz = minimize ? 1 : 0;
-#define KNN_SELW(R_) \
-  select_wave_kernel<R_><<<grid, 256, 0, s>>>(V, A, rows, nn, ldv, es, K, mz, out_val, out_idx, ldout, eo)
+#define KNN_SELW(R_)                                                                                          \
+  do {                                                                                                       \
+    if (K <= 32)                                                                                             \
+      select_wave_few_kernel<R_><<<grid, 256, 0, s>>>(V, A, rows, nn, ldv, es, K, mz, out_val, out_idx, ldout, \
+                                                      eo);                                                   \
+    else                                                                                                     \
+      select_wave_kernel<R_><<<grid, 256, 0, s>>>(V, A, rows, nn, ldv, es, K, mz, out_val, out_idx, ldout, eo); \
+  } while (0)
     if (n <= 64)
       KNN_SELW(1);
     else if (n <= 128)
