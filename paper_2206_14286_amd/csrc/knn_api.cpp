@@ -143,8 +143,10 @@ struct DevBuf {  // stream-ordered temporary from the library pool
   hipError_t alloc(size_t bytes, hipStream_t st) {
     s = st;
     hipMemPool_t pool;
-    hipError_t e = library_pool(&pool);
-    if (e != hipSuccess) return e;
+    if (library_pool(&pool) != hipSuccess) {  // no pool support: the device's default pool
+      (void)hipGetLastError();
+      return hipMallocAsync(&p, std::max<size_t>(bytes, 256), st);
+    }
     return hipMallocFromPoolAsync(&p, std::max<size_t>(bytes, 256), pool, st);
   }
   ~DevBuf() {
