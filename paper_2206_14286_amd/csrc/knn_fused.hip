@@ -41,13 +41,16 @@ namespace knn {
 
 namespace {
 
-// Bins leave the kernel through a per-wave LDS window of kWin consecutive bins x 64
-// queries (values and codes), written out as 64-byte row segments once the window
+// Bins leave the kernel through a per-wave LDS window of W consecutive bins x 64
+// queries (values and codes), written out as row segments of W bins once the window
 // is complete instead of one 4-byte store per query and bin.  Rows of the window
-// are padded to kWinStride words so the per-query writes fall in distinct banks.
-constexpr int kWin = 16;
-constexpr int kWinStride = kWin + 1;
-constexpr int kStageWords = 2 * 64 * kWinStride;  // per wave: values, then codes
+// are padded to W + 1 words (an odd stride) so the per-query writes fall in distinct
+// banks.  W = 16 (64-byte segments); 8 for the short FP8 tiles, whose kernel runs four
+// waves per SIMD and needs the LDS for a fourth workgroup per CU.
+template <int W>
+constexpr int stage_words() {
+  return 2 * 64 * (W + 1);  // per wave: values, then codes
+}
 
 template <int NG>
 struct TileGeom {
@@ -77,8 +80,13 @@ constexpr int stages() {
 }
 
 template <int DT, int NG>
+constexpr int win_bins() {
+  return (DT == DT_FP8 && NG == 4) ? 8 : 16;
+}
+
+template <int DT, int NG>
 constexpr int lds_bytes() {
-  return stages<DT, NG>() * TileGeom<NG>::kLdsBytes + kWaves * kStageWords * 4;
+  return stages<DT, NG>() * TileGeom<NG>::kLdsBytes + kWaves * stage_words<win_bins<DT, NG>()>() * 4;
 }
 
 // wait until at most N vector-memory loads of this wave are outstanding
@@ -384,31 +392,33 @@ __device__ __forceinline__ int32_t bin_code(unsigned u) {
 }
 
 // put one query's finished bin into the wave's output window
+template <int W>
 __device__ __forceinline__ void stage_bin(float* st, int qlocal, int bin, float v, unsigned u, float sign) {
-  st[qlocal * kWinStride + (bin & (kWin - 1))] = sign * v;
-  reinterpret_cast<int32_t*>(st)[64 * kWinStride + qlocal * kWinStride + (bin & (kWin - 1))] = bin_code(u);
+  st[qlocal * (W + 1) + (bin & (W - 1))] = sign * v;
+  reinterpret_cast<int32_t*>(st)[64 * (W + 1) + qlocal * (W + 1) + (bin & (W - 1))] = bin_code(u);
 }
 
-// Write the window of bins [wb, wb + kWin) clipped to the item's bins [b0, b1) for the
+// Write the window of bins [wb, wb + W) clipped to the item's bins [b0, b1) for the
 // wave's queries.  Lane (query row ql, part) writes bins wb + 4 part .. + 3 of its row,
-// so each store instruction covers 64-byte segments of 16 rows: as one 16-byte store
-// when the row offsets allow it (vec = 4), as two 8-byte stores (vec = 2) or four
+// so each store instruction covers W * 4-byte segments of 256 / W rows: as one 16-byte
+// store when the row offsets allow it (vec = 4), as two 8-byte stores (vec = 2) or four
 // 4-byte ones (vec = 1); bins outside the item are skipped one by one.
-template <int NCB>
+template <int NCB, int W>
 __device__ __forceinline__ void drain_window(const float* st, int wb, int b0, int b1, float* __restrict__ outV,
                                              int32_t* __restrict__ outA, int64_t ldo, int64_t wq0, int64_t M,
                                              int vec, int lane) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int32_t* sa = reinterpret_cast<const int32_t*>(st) + 64 * kWinStride;
+  constexpr int P = W / 4, RPI = 64 / P;  // parts per row, rows per instruction
+  const int32_t* sa = reinterpret_cast<const int32_t*>(st) + 64 * (W + 1);
 #pragma unroll
-  for (int s = 0; s < NCB * 32 / 16; ++s) {
-    const int ql = 16 * s + (lane >> 2), part = lane & 3;
+  for (int s = 0; s < NCB * 32 / RPI; ++s) {
+    const int ql = RPI * s + lane / P, part = lane % P;
     const int64_t q = wq0 + ql;
     const int pb = wb + 4 * part;
-    const float* sv = st + ql * kWinStride + 4 * part;
-    const int32_t* si = sa + ql * kWinStride + 4 * part;
+    const float* sv = st + ql * (W + 1) + 4 * part;
+    const int32_t* si = sa + ql * (W + 1) + 4 * part;
     if (q < M) {
       float* ov = outV + q * ldo + pb;
       int32_t* oa = outA + q * ldo + pb;
@@ -481,7 +491,8 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int h = lane >> 5, ql = lane & 31;
-  float* stage = reinterpret_cast<float*>(lds + S * G::kLdsBytes) + wave * kStageWords;
+  constexpr int W = win_bins<DT, NG>();
+  float* stage = reinterpret_cast<float*>(lds + S * G::kLdsBytes) + wave * stage_words<W>();
   // widest store the output rows allow (window starts are multiples of 4 bins)
   const uintptr_t oaddr = reinterpret_cast<uintptr_t>(outV) | reinterpret_cast<uintptr_t>(outA);
   const int vec_ok = ((oaddr & 15) == 0 && (ldo & 3) == 0) ? 4 : (((oaddr & 7) == 0 && (ldo & 1) == 0) ? 2 : 1);
@@ -578,7 +589,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
         const float ov = __shfl_xor(sv, 32);
         const unsigned ou = __shfl_xor(su, 32);
         const bool take = (ov > kv) || (ov == kv && ou < ku);
-        stage_bin(stage, h * 32 + ql, cur_bin, take ? ov : kv, take ? ou : ku, sign);
+        stage_bin<W>(stage, h * 32 + ql, cur_bin, take ? ov : kv, take ? ou : ku, sign);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
           bv[cb] = -INFINITY;
@@ -590,13 +601,13 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
           float mv;
           unsigned mu;
           merge_halves(bv[cb], bu[cb], h, mv, mu);
-          if (h == (cb & 1)) stage_bin(stage, cb * 32 + ql, cur_bin, mv, mu, sign);
+          if (h == (cb & 1)) stage_bin<W>(stage, cb * 32 + ql, cur_bin, mv, mu, sign);
           bv[cb] = -INFINITY;
           bu[cb] = kNoUnit;
         }
       }
-      if ((cur_bin & (kWin - 1)) == kWin - 1 || cur_bin == b1 - 1)
-        drain_window<NCB>(stage, cur_bin & ~(kWin - 1), (int)b0, (int)b1, outV, outA, ldo, wq0, M, vec_ok, lane);
+      if ((cur_bin & (W - 1)) == W - 1 || cur_bin == b1 - 1)
+        drain_window<NCB, W>(stage, cur_bin & ~(W - 1), (int)b0, (int)b1, outV, outA, ldo, wq0, M, vec_ok, lane);
       ++cur_bin;
       cursor.advance();
     };
@@ -687,9 +698,9 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     }
     const bool lane_on = h == 0 || NCB == 2;
     auto flush_row = [&]() {
-      if (lane_on) stage_bin(stage, h * 32 + ql, cur_bin, sv, su, sign);
-      if ((cur_bin & (kWin - 1)) == kWin - 1 || cur_bin == b1 - 1)
-        drain_window<NCB>(stage, cur_bin & ~(kWin - 1), (int)b0, (int)b1, outV, outA, ldo, wq0, M, vec_ok, lane);
+      if (lane_on) stage_bin<W>(stage, h * 32 + ql, cur_bin, sv, su, sign);
+      if ((cur_bin & (W - 1)) == W - 1 || cur_bin == b1 - 1)
+        drain_window<NCB, W>(stage, cur_bin & ~(W - 1), (int)b0, (int)b1, outV, outA, ldo, wq0, M, vec_ok, lane);
       sv = -INFINITY;
       su = kNoUnit;
       ++cur_bin;
@@ -806,11 +817,12 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
 }
 
 // Occupancy: the short FP8 tiles have the least matrix work per tile to hide the bin
-// update behind, and the BF16 depth-128 kernel overlaps three waves' bin updates;
-// both are held to 3 waves per SIMD (<= 168 VGPRs).
+// update behind: the depth-128 FP8 kernel runs 4 waves per SIMD (<= 128 VGPRs; its
+// output windows of 8 bins leave the LDS for four workgroups per CU), depth 64 FP8
+// and the BF16 depth-128 kernel 3 (<= 168 VGPRs).
 template <int DT, int NG>
 constexpr int min_waves() {
-  return ((DT == DT_FP8 && NG <= 4) || (DT == DT_BF16 && NG == 8)) ? 3 : 1;
+  return (DT == DT_FP8 && NG == 4) ? 4 : (((DT == DT_FP8 && NG < 4) || (DT == DT_BF16 && NG == 8)) ? 3 : 1);
 }
 
 template <int DT, int NG, int NCB>
