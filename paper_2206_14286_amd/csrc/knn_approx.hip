@@ -18,8 +18,9 @@
 //     merged with an LDS atomic max: the larger key is the better score and, for equal
 //     scores, the lower index.  Adding +0 maps -0 to +0 so the two zeros tie.
 //   approx_cols_kernel: bins down the strided dimension (each column is one slice).  A
-//     thread owns one column and walks its rows in order through a run of bins; a wave
-//     reads consecutive columns of one row per load.
+//     lane owns one column and walks its rows in order through a run of bins; a wave
+//     reads 64 consecutive columns of one row per load.  Bins of at least 256 rows are
+//     split into quarters over the workgroup's four waves, merged in order through LDS.
 #include <algorithm>
 #include <cmath>
 
