@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kApproxThreads) void approx_rows_kernel(const T* __
 template <typename T, bool MIN>
 __device__ __forceinline__ void scan_rows(const T* __restrict__ col, int64_t ld, int64_t rs, int64_t re, float& bv,
                                           int64_t& bj) {
-  constexpr int UNR = 8;
+  constexpr int UNR = 16;
   bv = widen(col[rs * ld]);
   bj = rs;
   for (int64_t j = rs + 1; j < re; j += UNR) {
