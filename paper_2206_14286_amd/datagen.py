@@ -38,8 +38,8 @@ def normal(n: int, d: int, seed: int, scale: float = 1.0) -> np.ndarray:
 
 def normal_device(n: int, d: int, seed: int, scale: float = 1.0, dtype=None, device: str = "cuda"):
     """i.i.d. N(0, scale^2) rows drawn on the device with torch's seeded generator: for
-    inputs of many GB (the batched and backward workloads) that are timed, not checked
-    element by element against the oracle."""
+    inputs of many GB (the batched and backward workloads); the parity tests copy them back
+    to the host to check sampled outputs against the oracle."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(seed)

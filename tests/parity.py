@@ -97,3 +97,63 @@ def check_topk(Q, X, metric, K, gpu_v, gpu_i, ora, dpad, u=2.0 ** -23, value_rto
             ok = (s64[i, r] <= kth + t) if mn else (s64[i, r] >= kth - t)
             assert ok, f"query {i}: returned row {gi[i, r]} is worse than the K-th by more than the bound"
     assert all(len(set(row.tolist())) == K for row in gi), "duplicate rows in a top-K"
+
+
+def check_rerank(Q, X, metric, compute, K, L, Kr, vals, idx, dpad, u):
+    """Rerank parity against the oracle's definition: the top-Kr bin winners of the
+    quantised search, rescored in FP64 from the original rows, best K kept.  For every
+    query, under the rounding bounds of both stages:
+      * every returned value is the FP32 score of its row, best first;
+      * every returned row could be a candidate: its quantised score is within the
+        bound of its bin's winner, and that bin is not clearly outside the top Kr;
+      * every sure candidate (a clear winner of a bin clearly inside the top Kr) whose
+        FP64 score clearly beats the K-th returned score is returned.
+    Q, X: the caller's rows (float32); vals, idx: the GPU's M x K output.  Returns the
+    number of sure rows checked."""
+    M, D = Q.shape
+    N = X.shape[0]
+    vals = np.asarray(vals, np.float64)
+    idx = np.asarray(idx, np.int64)
+    mn = oracle.minimize_for(metric)
+    sign = 1.0 if mn else -1.0  # ascending sign*value = better first
+    qi = np.repeat(np.arange(M), K)
+    # returned values: FP32 scores of the returned rows, sorted best first
+    s64, mag = oracle.pair_scores(Q, X, metric, qi, idx.ravel())
+    s64, mag = s64.reshape(M, K), mag.reshape(M, K)
+    g32 = gamma(D)
+    tol32 = np.maximum(1e-5 * np.abs(s64), g32 * mag) + 1e-30
+    np.testing.assert_array_less(np.abs(vals - s64), tol32)
+    assert np.all(np.diff(sign * vals, axis=1) >= 0), "rerank output not sorted best first"
+    assert all(len(set(row.tolist())) == K for row in idx), "duplicate rows in a top-K"
+    # quantised search of the oracle: bins and their winners
+    Qq = oracle.quantize_like_library(Q, metric, compute)
+    Xq = oracle.quantize_like_library(X, metric, compute)
+    mo = "mips" if metric == "cosine" else metric
+    ora = oracle.search(Qq, Xq, mo, L, Kr, bins=True)
+    gq = gamma(dpad, u)
+    starts = np.array([oracle.bin_start(b, N, L) for b in range(L + 1)])
+    sq, mq = oracle.pair_scores(Qq, Xq, mo, qi, idx.ravel())
+    sq, mq = sq.reshape(M, K), mq.reshape(M, K)
+    n_sure_checked = 0
+    for i in range(M):
+        bv, bm = ora["bin_v"][i], ora["bin_mag"][i]
+        order = np.lexsort((np.arange(L), sign * bv))
+        kth, k1 = order[Kr - 1], order[Kr] if Kr < L else order[Kr - 1]
+        # returned rows are possible candidates
+        b = np.searchsorted(starts, idx[i], side="right") - 1
+        worse_than_winner = sign * (sq[i] - bv[b])
+        assert np.all(worse_than_winner <= gq * (mq[i] + bm[b]) + 1e-30), f"query {i}: a row that cannot win its bin"
+        outside = sign * (bv[b] - bv[kth])
+        assert np.all(outside <= gq * (bm[b] + bm[kth]) + 1e-30), f"query {i}: a bin outside the top Kr"
+        # sure candidates that clearly beat the K-th returned score must be returned
+        clear_in = sign * (bv[k1] - bv) > gq * (bm + bm[k1]) if Kr < L else np.ones(L, bool)
+        clear_win = np.abs(bv - ora["bin2_v"][i]) > gq * (bm + ora["bin2_mag"][i])
+        sure = ora["bin_i"][i][clear_in & clear_win]
+        if sure.size == 0:
+            continue
+        cs, cm = oracle.pair_scores(Q, X, metric, np.full(sure.size, i), sure)
+        beats = sign * (s64[i, K - 1] - cs) > g32 * (cm + mag[i, K - 1]) + 1e-5 * np.abs(cs)
+        must = set(sure[beats].tolist())
+        n_sure_checked += len(must)
+        assert must <= set(idx[i].tolist()), f"query {i}: missing rows {sorted(must - set(idx[i].tolist()))}"
+    return n_sure_checked

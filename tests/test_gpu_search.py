@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_2206_14286_amd import datagen, knn
-from parity import check_bins, check_topk, gamma
+from parity import check_bins, check_rerank, check_topk, gamma
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -211,14 +211,9 @@ RERANK_CASES = [
 
 @pytest.mark.parametrize("metric,compute,in_dtype,D,Kr", RERANK_CASES)
 def test_rerank_matches_oracle(metric, compute, in_dtype, D, Kr):
-    """Rerank parity against the oracle's definition: the top-Kr bin winners of the
-    quantised search, rescored in FP64 from the original rows, best K kept.  For every
-    query, under the rounding bounds of both stages:
-      * every returned value is the FP32 score of its row, best first;
-      * every returned row could be a candidate: its quantised score is within the
-        bound of its bin's winner, and that bin is not clearly outside the top Kr;
-      * every sure candidate (a clear winner of a bin clearly inside the top Kr) whose
-        FP64 score clearly beats the K-th returned score is returned."""
+    """Rerank parity against the oracle's definition (the top-Kr bin winners of the
+    quantised search, rescored in FP64 from the original rows, best K kept), under the
+    rounding bounds of both stages; the rules are listed in ``parity.check_rerank``."""
     M, N, K, L = 64, 20000, 10, 1024
     _log(f"rerank parity {metric} {compute} in={in_dtype} D={D} Kr={Kr}")
     if metric == "l2":
@@ -231,47 +226,7 @@ def test_rerank_matches_oracle(metric, compute, in_dtype, D, Kr):
     tdt = torch.bfloat16 if in_dtype == "bf16" else torch.float32
     db = knn.Database(to_dev(X, tdt), metric, compute)
     vals, idx = db.search(to_dev(Q, tdt), K, L, rerank=Kr)
-    vals, idx = vals.cpu().numpy().astype(np.float64), idx.cpu().numpy().astype(np.int64)
-    mn = oracle.minimize_for(metric)
-    sign = 1.0 if mn else -1.0  # ascending sign*value = better first
-    qi = np.repeat(np.arange(M), K)
-    # returned values: FP32 scores of the returned rows, sorted best first
-    s64, mag = oracle.pair_scores(Q, X, metric, qi, idx.ravel())
-    s64, mag = s64.reshape(M, K), mag.reshape(M, K)
-    g32 = gamma(D)
-    tol32 = np.maximum(1e-5 * np.abs(s64), g32 * mag) + 1e-30
-    np.testing.assert_array_less(np.abs(vals - s64), tol32)
-    assert np.all(np.diff(sign * vals, axis=1) >= 0), "rerank output not sorted best first"
-    # quantised search of the oracle: bins and their winners
-    Qq = oracle.quantize_like_library(Q, metric, compute)
-    Xq = oracle.quantize_like_library(X, metric, compute)
-    mo = "mips" if metric == "cosine" else metric
-    ora = oracle.search(Qq, Xq, mo, L, Kr, bins=True)
-    gq = gamma(dpad_of(D, compute), U_BOUND[compute])
-    starts = np.array([oracle.bin_start(b, N, L) for b in range(L + 1)])
-    sq, mq = oracle.pair_scores(Qq, Xq, mo, qi, idx.ravel())
-    sq, mq = sq.reshape(M, K), mq.reshape(M, K)
-    n_sure_checked = 0
-    for i in range(M):
-        bv, bm = ora["bin_v"][i], ora["bin_mag"][i]
-        order = np.lexsort((np.arange(L), sign * bv))
-        kth, k1 = order[Kr - 1], order[Kr] if Kr < L else order[Kr - 1]
-        # returned rows are possible candidates
-        b = np.searchsorted(starts, idx[i], side="right") - 1
-        worse_than_winner = sign * (sq[i] - bv[b])
-        assert np.all(worse_than_winner <= gq * (mq[i] + bm[b]) + 1e-30), f"query {i}: a row that cannot win its bin"
-        outside = sign * (bv[b] - bv[kth])
-        assert np.all(outside <= gq * (bm[b] + bm[kth]) + 1e-30), f"query {i}: a bin outside the top Kr"
-        # sure candidates that clearly beat the K-th returned score must be returned
-        clear_in = sign * (bv[k1] - bv) > gq * (bm + bm[k1]) if Kr < L else np.ones(L, bool)
-        clear_win = np.abs(bv - ora["bin2_v"][i]) > gq * (bm + ora["bin2_mag"][i])
-        sure = ora["bin_i"][i][clear_in & clear_win]
-        if sure.size == 0:
-            continue
-        cs, cm = oracle.pair_scores(Q, X, metric, np.full(sure.size, i), sure)
-        beats = sign * (s64[i, K - 1] - cs) > g32 * (cm + mag[i, K - 1]) + 1e-5 * np.abs(cs)
-        must = set(sure[beats].tolist())
-        n_sure_checked += len(must)
-        assert must <= set(idx[i].tolist()), f"query {i}: missing rows {sorted(must - set(idx[i].tolist()))}"
+    n_sure_checked = check_rerank(Q, X, metric, compute, K, L, Kr, vals.cpu().numpy(), idx.cpu().numpy(),
+                                  dpad_of(D, compute), U_BOUND[compute])
     _log(f"  {n_sure_checked} sure rows checked")
     assert n_sure_checked >= M * K // 4
