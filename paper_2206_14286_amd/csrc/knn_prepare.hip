@@ -110,14 +110,17 @@ __device__ void prepare_row(const Src& load, bool valid, int64_t r, int64_t dst,
 }
 
 // The 64 rows of a workgroup are consecutive in the source, so they are first copied
-// into LDS with coalesced loads (consecutive threads, consecutive elements), widened to
-// FP32 (exact), one row per LDS row of D + 1 words (an odd stride: thread t reading
-// element d of its own row hits bank (t (D + 1) + d) mod 64, a different bank per
-// thread).  Each thread then prepares its own row from LDS with the arithmetic above.
+// into LDS with coalesced loads (consecutive threads, consecutive elements) by all 256
+// threads, 8 loads each in flight (one trip to memory for rows of up to 128 FP32
+// elements), widened to FP32 (exact), one row per LDS row of D + 1 words (an odd
+// stride: thread t reading element d of its own row hits bank (t (D + 1) + d) mod 64,
+// a different bank per thread).  The first 64 threads then prepare one row each from
+// LDS with the arithmetic above.
 constexpr int kPrepRows = 64;
+constexpr int kPrepThreads = 256;
 
 template <int CDT>
-__global__ __launch_bounds__(kPrepRows) void prepare_kernel(const void* src, int in_dt, int64_t rows, int D, int ng,
+__global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void* src, int in_dt, int64_t rows, int D, int ng,
                                                              int metric, int database, unsigned char* tiles,
                                                              int64_t n_rows_padded, float* orig_half_norm,
                                                              float* orig_rnorm) {
@@ -140,16 +143,16 @@ __global__ __launch_bounds__(kPrepRows) void prepare_kernel(const void* src, int
     const int per = 16 / esz, total16 = total / per;
     const u32x4* s16 = reinterpret_cast<const u32x4*>(static_cast<const unsigned char*>(src) + base * esz);
     constexpr int U = 8;
-    for (int i0 = 0; i0 < total16; i0 += kPrepRows * U) {
+    for (int i0 = 0; i0 < total16; i0 += kPrepThreads * U) {
       u32x4 w[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * kPrepRows + t;
+        const int i = i0 + u * kPrepThreads + t;
         w[u] = i < total16 ? s16[i] : u32x4{0u, 0u, 0u, 0u};
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * kPrepRows + t;
+        const int i = i0 + u * kPrepThreads + t;
         if (i >= total16) continue;
         if (in_dt == DT_F32) {
 #pragma unroll
@@ -165,23 +168,23 @@ __global__ __launch_bounds__(kPrepRows) void prepare_kernel(const void* src, int
     }
   } else {
     constexpr int U = 8;
-    for (int i0 = 0; i0 < total; i0 += kPrepRows * U) {
+    for (int i0 = 0; i0 < total; i0 += kPrepThreads * U) {
       float x[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * kPrepRows + t;
+        const int i = i0 + u * kPrepThreads + t;
         x[u] = i < total ? load_elem(src, in_dt, base + i) : 0.f;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * kPrepRows + t;
+        const int i = i0 + u * kPrepThreads + t;
         if (i < total) put(i, x[u]);
       }
     }
   }
   __syncthreads();
   const int64_t r = r0 + t;
-  if (r >= n_rows_padded) return;
+  if (t >= kPrepRows || r >= n_rows_padded) return;
   prepare_row<CDT>(LdsRow{stage + t * (D + 1)}, src != nullptr && r < rows, r, r, D, ng, metric, database != 0,
                    tiles, orig_half_norm, orig_rnorm);
 }
@@ -221,13 +224,13 @@ hipError_t launch_prepare(const void* src, int in_dt, int64_t rows, int D, int m
     if (e != hipSuccess) return e;
   }
   if (compute == DT_F32)
-    prepare_kernel<DT_F32><<<grid, kPrepRows, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+    prepare_kernel<DT_F32><<<grid, kPrepThreads, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
                                                         orig_half_norm, orig_rnorm);
   else if (compute == DT_BF16)
-    prepare_kernel<DT_BF16><<<grid, kPrepRows, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+    prepare_kernel<DT_BF16><<<grid, kPrepThreads, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
                                                          orig_half_norm, orig_rnorm);
   else
-    prepare_kernel<DT_FP8><<<grid, kPrepRows, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
+    prepare_kernel<DT_FP8><<<grid, kPrepThreads, lds, s>>>(src, in_dt, rows, D, ng, metric, database, tiles, n,
                                                         orig_half_norm, orig_rnorm);
   return hipGetLastError();
 }
