@@ -75,6 +75,8 @@ def test_approx_top_k_argument_checks(K):
     assert call(L=101) == 1
     assert call(k=101) == 1
     assert call(k=2000, cols=5000, ld=5000, L=3000) == 1
+    assert call(k=1025, cols=5000, ld=5000, L=3000) == 1 and b"1024" in lib.knn_last_error()
+    assert call(k=1024, cols=5000, ld=5000, L=3000, rows=0) == 0  # the largest K passes the checks
     assert call(L=0, r=1.5) == 1
     assert call(dim=0, k=5, L=10) == 1  # the reduced dimension has 4 entries
     # no slices: succeeds without touching the device

@@ -206,6 +206,7 @@ RERANK_CASES = [
     ("mips", "fp8", "fp32", 256, 300),
     ("l2", "fp8", "bf16", 100, 600),
     ("mips", "bf16", "fp32", 33, 65),
+    ("mips", "bf16", "fp32", 64, 1024),   # the largest rerank depth (= L)
 ]
 
 
