@@ -233,6 +233,22 @@ def test_recall_monte_carlo_at_mips_small_shape():
     assert recs.mean() > bound
 
 
+def test_exact_expectation_bins_at_the_sift_shape():
+    """N = 10^6, K = 10 (the SIFT-shaped workload).  With N much larger than K, drawing the
+    neighbours' rows without replacement barely differs from placing them independently,
+    so the exact balanced-bin expectation must sit within 1e-4 of the closed form
+    L (1 - (1 - 1/L)^K) / K, and above the paper's bound.  L = 176 (eq. l:approx) gives
+    0.9748; the smallest L whose exact expectation reaches 0.95 is 88."""
+    N, K = 1_000_000, 10
+    for L in (87, 88, 176):
+        exact = oracle.recall_exact_balanced(N, L, K)
+        indep = L * (1.0 - (1.0 - 1.0 / L) ** K) / K
+        assert abs(exact - indep) < 1e-4
+        assert exact >= oracle.recall_bound_paper(K, L)
+    assert abs(oracle.recall_exact_balanced(N, 176, K) - 0.97482) < 1e-5
+    assert oracle.recall_exact_balanced(N, 88, K) >= 0.95 > oracle.recall_exact_balanced(N, 87, K)
+
+
 def test_bins_for_recall():
     """eq. l:approx: K = 10, r = 0.95 -> L >= 1/(1 - 0.95^(1/9)) = 175.97 -> 176; the
     first-order form (K-1)/(1-r) gives 180; the result is the smallest L meeting eq. recall."""
