@@ -489,6 +489,10 @@ def main():
         s64, _ = oracle.pair_scores(Q[sample], X, w["metric"], np.repeat(np.arange(len(sample)), K), r["idx_sample"].ravel())
         r["recall_at_10"] = float(oracle.recall(r["idx_sample"], ex["ex_i"]).mean())
         r["recall_at_10_tie_aware"] = float(oracle.recall_tie_aware(s64.reshape(-1, K), kth, True).mean())
+        # returned values against the FP64 scores of the returned rows
+        err = np.abs(r["val_sample"].astype(np.float64).ravel() - s64)
+        r["max_score_abs_err"] = float(err.max())
+        r["max_score_rel_err"] = float((err / np.maximum(np.abs(s64), 1e-30)).max())
         del r["idx_sample"], r["val_sample"]
 
     head = results[args.compute]
@@ -510,6 +514,7 @@ def main():
                    "compute": args.compute, "rerank_k": head["rerank_k"]},
         "recall_at_10": head["recall_at_10"],
         "recall_at_10_tie_aware": head["recall_at_10_tie_aware"],
+        "max_score_rel_err": head["max_score_rel_err"],
         "oracle_fp64_recall_at_10_tie_aware": oracle_recall,
         "roofline": {
             "bound": "mfma",
@@ -521,6 +526,10 @@ def main():
             "kernel": "fused distance GEMM + bin reduce",
             "kernel_ms": head["fused_kernel_ms"],
             "flops_per_launch": flops,
+            # from the committed counter runs of this kernel (null once the sources change):
+            # matrix-pipe busy fraction and the clock it ran at (the nominal peak assumes 2.4 GHz)
+            "mfma_busy": _counter_figure(f"mfma_busy[{args.compute}]"),
+            "est_clock_ghz": _counter_figure(f"est_clock_ghz[{args.compute}]"),
         },
         "variants": {k: v for k, v in results.items() if k != args.compute},
     }
