@@ -608,6 +608,14 @@ def main():
         line["cpu_baseline"] = {"value": S / dt, "unit": "queries/s", "cores": threads, "kind": "oracle",
                                 "sample": f"first {S} of the {M} queries against all {N} rows "
                                           f"(FP64 scores + bins + top-K), {dt:.1f} s"}
+        # the exact ground truth beside it: a full sort of all N scores per query
+        n1 = min(M, max(2 * threads, 16))
+        t0 = time.perf_counter()
+        oracle.search(Q[:n1], X, w["metric"], L, K, exact=True, nthreads=threads)
+        dte = time.perf_counter() - t0
+        line["cpu_baseline"]["exact_knn_value"] = n1 / dte
+        line["cpu_baseline"]["exact_knn_sample"] = (f"first {n1} queries: FP64 scores, bins + top-K and a full "
+                                                    f"sort of all {N} scores, {dte:.1f} s")
     print(json.dumps(line), flush=True)
 
 
