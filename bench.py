@@ -533,6 +533,8 @@ def main():
         },
         "variants": {k: v for k, v in results.items() if k != args.compute},
     }
+    if line["roofline"]["traffic"] is not None:  # measured HBM bytes over the kernel's time
+        line["roofline"]["traffic_gb_s"] = line["roofline"]["traffic"] / (head["fused_kernel_ms"] * 1e-3) / 1e9
     # context for the fraction of peak: a large square BF16 GEMM from the vendor library
     # (hipBLASLt through torch.matmul) on the same GPU, same nominal peak
     A = torch.randn((8192, 8192), device="cuda").to(torch.bfloat16)
