@@ -533,6 +533,9 @@ def main():
         },
         "variants": {k: v for k, v in results.items() if k != args.compute},
     }
+    ck = line["roofline"]["est_clock_ghz"]
+    if ck:  # the same rate against the peak at the clock the counters saw (peak assumes 2.4 GHz)
+        line["roofline"]["frac_at_est_clock"] = head["fused_frac_of_peak"] * 2.4 / ck
     if line["roofline"]["traffic"] is not None:  # measured HBM bytes over the kernel's time
         line["roofline"]["traffic_gb_s"] = line["roofline"]["traffic"] / (head["fused_kernel_ms"] * 1e-3) / 1e9
     # context for the fraction of peak: a large square BF16 GEMM from the vendor library
