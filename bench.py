@@ -425,7 +425,7 @@ def main():
                          "scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding); "
+        print("bench.py measures one GPU: the library has no multi-GPU path (sharding is a design only); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
