@@ -554,7 +554,7 @@ def main():
         target = results["fp32"]["recall_at_10_tie_aware"]
         pick = None
         db8 = knn.Database(Xd, w["metric"], "fp8")
-        for L8, Kr8 in ((L, 40), (2 * L, 64), (4 * L, 100), (8 * L, 160), (16 * L, 256)):
+        for L8, Kr8 in ((L, 40), (2 * L, 64), (2 * L, 100), (4 * L, 100), (8 * L, 160), (16 * L, 256)):
             idx8 = db8.search(Qd[sample_t], K, L8, rerank=Kr8)[1].cpu().numpy()
             s64, _ = oracle.pair_scores(Q[sample], X, w["metric"], np.repeat(np.arange(len(sample)), K), idx8.ravel())
             rec = float(oracle.recall_tie_aware(s64.reshape(-1, K), kth, True).mean())
