@@ -241,8 +241,8 @@ def row_cosine_glove(torch, knn, datagen, oracle, steps, warmup, sample_n=256):
             # more bins as bins of 2^W rows (Algorithm 1's ShiftRight form) where N allows:
             # 64- and 32-row bins keep every bin boundary on a 32-row tile edge
             more = [N // r if N % r == 0 else m * L for r, m in ((64, 2), (32, 4))]
-            for Lc, rr in ((L, 2 * K), (L, 4 * K), (more[0], 2 * K), (more[0], 4 * K), (more[1], 2 * K),
-                           (more[1], 4 * K)):
+            for Lc, rr in ((L, 2 * K), (L, 4 * K), (more[0], 2 * K), (more[0], 3 * K), (more[0], 4 * K),
+                           (more[1], 2 * K), (more[1], 4 * K)):
                 rec = recall_of(db.search(Qd[st], K, Lc, rerank=rr)[1].cpu().numpy())
                 log(f"  fp8 L={Lc} rerank {rr}: recall {rec:.4f}")
                 if rec >= out["fp32"]["recall_tie_aware"]:
