@@ -64,7 +64,7 @@ def test_full_size_cosine_glove_sampled():
     _free()
 
     db8 = knn.Database(Xd, "cosine", "fp8")
-    for Lc, Kr in ((L, 2 * K), (N // 64, 4 * K)):
+    for Lc, Kr in ((L, 2 * K), (N // 64, 3 * K)):
         _log(f"cosine_glove fp8 + rerank: L={Lc} Kr={Kr}")
         vals, idx = db8.search(Qd, K, Lc, rerank=Kr)
         torch.cuda.synchronize()
