@@ -64,6 +64,12 @@ CASES = [
     ("rows_select_many_ties", 3, 300000, 1, "fp32", 10, 20000, False, True, 0, "ints", -1),
     ("cols_select_strided", 60000, 16, 0, "fp32", 50, 3000, False, True, 0, "normal", -1),
     ("cols_split_bf16_min_strided", 9001, 65, 0, "bf16", 5, 7, True, False, 3, "ints", -1),
+    # top-K over 1025 .. 4096 winners with K <= 32 (ragged lengths, ties, minimisation,
+    # strided columns)
+    ("rows_block_select_ragged_ties_min", 7, 1100, 1, "fp32", 32, 1100, True, True, 0, "ints", -1),
+    ("rows_block_select_16", 5, 3001, 1, "bf16", 17, 3001, False, True, 2, "normal", -1),
+    ("rows_block_select_bins", 6, 40000, 1, "fp32", 10, 4096, False, True, 0, "ints", -1),
+    ("cols_block_select_strided", 2500, 9, 0, "bf16", 10, 2500, False, True, 1, "ints", -1),
     # the largest K the op takes (1024): key-range select, one-wave select, columns
     ("rows_max_K_range_select", 5, 5000, 1, "fp32", 1024, 5000, False, True, 0, "normal", -1),
     ("rows_max_K_wave_select_ties", 3, 1024, 1, "fp32", 1024, 1024, True, True, 0, "ints", -1),
