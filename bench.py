@@ -224,14 +224,14 @@ def row_cosine_glove(torch, knn, datagen, oracle, steps, warmup, sample_n=256):
     st = torch.from_numpy(sample).cuda()
     log("cosine_glove: oracle exact on", sample_n, "queries")
     ex = oracle.search(Q[sample], X, "cosine", L, K, exact=True)
-    kth = ex["ex_v"][:, -1]
+    exv = ex["ex_v"]
 
     def recall_of(idx):
         s64, _ = oracle.pair_scores(Q[sample], X, "cosine", np.repeat(np.arange(sample_n), K), idx.ravel())
-        return float(oracle.recall_tie_aware(s64.reshape(-1, K), kth, False).mean())
+        return float(oracle.recall_tie_aware(s64.reshape(-1, K), exv, False).mean())
 
     out = {"workload": "cosine_glove", "M": M, "N": N, "D": D, "K": K, "L": L,
-           "oracle_fp64_recall_tie_aware": float(oracle.recall_tie_aware(ex["top_v"], kth, False).mean())}
+           "oracle_fp64_recall_tie_aware": float(oracle.recall_tie_aware(ex["top_v"], exv, False).mean())}
     o = (torch.empty((M, K), dtype=torch.float32, device="cuda"), torch.empty((M, K), dtype=torch.int32, device="cuda"))
     bins = (torch.empty((M, L), dtype=torch.float32, device="cuda"), torch.empty((M, L), dtype=torch.int32, device="cuda"))
     for compute in ("fp32", "fp8"):
@@ -458,12 +458,12 @@ def main():
     # recall against the exact FP64 K-NN on a sample of queries (outside the timed region)
     log("recall sample", len(sample))
     ex = oracle.search(Q[sample], X, w["metric"], L, K, exact=True)
-    kth = ex["ex_v"][:, -1]
-    oracle_recall = float(oracle.recall_tie_aware(ex["top_v"], kth, True).mean())
+    exv = ex["ex_v"]
+    oracle_recall = float(oracle.recall_tie_aware(ex["top_v"], exv, True).mean())
 
     def sample_recall(idx):
         s64, _ = oracle.pair_scores(Q[sample], X, w["metric"], np.repeat(np.arange(len(sample)), K), idx.ravel())
-        return float(oracle.recall_tie_aware(s64.reshape(-1, K), kth, True).mean())
+        return float(oracle.recall_tie_aware(s64.reshape(-1, K), exv, True).mean())
 
     # rerank depth of the headline form: the smallest that keeps the method's own recall
     if args.compute == "fp32":
@@ -488,7 +488,7 @@ def main():
     for comp, r in results.items():
         s64, _ = oracle.pair_scores(Q[sample], X, w["metric"], np.repeat(np.arange(len(sample)), K), r["idx_sample"].ravel())
         r["recall_at_10"] = float(oracle.recall(r["idx_sample"], ex["ex_i"]).mean())
-        r["recall_at_10_tie_aware"] = float(oracle.recall_tie_aware(s64.reshape(-1, K), kth, True).mean())
+        r["recall_at_10_tie_aware"] = float(oracle.recall_tie_aware(s64.reshape(-1, K), exv, True).mean())
         # returned values against the FP64 scores of the returned rows
         err = np.abs(r["val_sample"].astype(np.float64).ravel() - s64)
         r["max_score_abs_err"] = float(err.max())
@@ -557,7 +557,7 @@ def main():
         for L8, Kr8 in ((L, 40), (2 * L, 64), (2 * L, 100), (4 * L, 100), (8 * L, 160), (16 * L, 256)):
             idx8 = db8.search(Qd[sample_t], K, L8, rerank=Kr8)[1].cpu().numpy()
             s64, _ = oracle.pair_scores(Q[sample], X, w["metric"], np.repeat(np.arange(len(sample)), K), idx8.ravel())
-            rec = float(oracle.recall_tie_aware(s64.reshape(-1, K), kth, True).mean())
+            rec = float(oracle.recall_tie_aware(s64.reshape(-1, K), exv, True).mean())
             log(f"fp8 L={L8} rerank={Kr8}: recall {rec:.4f} (target {target:.4f})")
             pick = (L8, Kr8, rec)
             if rec >= target:
@@ -579,8 +579,8 @@ def main():
         s64, _ = oracle.pair_scores(Q[sample], X, w["metric"], np.repeat(np.arange(len(sample)), K),
                                     re_["idx_sample"].ravel())
         re_["recall_at_10"] = float(oracle.recall(re_["idx_sample"], ex["ex_i"]).mean())
-        re_["recall_at_10_tie_aware"] = float(oracle.recall_tie_aware(s64.reshape(-1, K), kth, True).mean())
-        re_["oracle_fp64_recall_at_10_tie_aware"] = float(oracle.recall_tie_aware(exe["top_v"], kth, True).mean())
+        re_["recall_at_10_tie_aware"] = float(oracle.recall_tie_aware(s64.reshape(-1, K), exv, True).mean())
+        re_["oracle_fp64_recall_at_10_tie_aware"] = float(oracle.recall_tie_aware(exe["top_v"], exv, True).mean())
         re_["expected_recall_balanced_bins"] = oracle.recall_exact_balanced(N, Le, K)
         re_["expected_recall_paper_bound"] = oracle.recall_bound_paper(K, Le)
         del re_["idx_sample"], re_["val_sample"]

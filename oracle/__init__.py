@@ -148,7 +148,8 @@ def search(Q, X, metric, L: int, K: int, *, bins: bool = False, exact: bool = Fa
     """Approximate search of the paper (scores -> Algorithm 1 -> top-K of the bins), in FP64.
 
     Returns a dict with ``top_v``/``top_i`` (M x K), and with ``bins=True`` the bin winners
-    ``bin_v``/``bin_i``/``bin_mag`` and the runner-ups ``bin2_v``/``bin2_mag`` (M x L); with
+    ``bin_v``/``bin_i``/``bin_mag`` (M x L), the best score among each bin's other rows
+    ``bin2_v`` and the largest magnitude among those other rows ``bin2_mag``; with
     ``exact=True`` the exact K-NN ``ex_v``/``ex_i`` (M x K) by a full sort of all N scores.
     """
     Q, X = _f32(Q), _f32(X)
@@ -300,12 +301,25 @@ def recall(retrieved, truth) -> np.ndarray:
     return out
 
 
-def recall_tie_aware(retrieved_scores, kth_best, minimize: bool) -> np.ndarray:
-    """Fraction of retrieved rows whose exact score is at least as good as the exact K-th best."""
+def recall_tie_aware(retrieved_scores, exact_scores, minimize: bool) -> np.ndarray:
+    """eq. recall-def when the exact K-NN is not unique (ties at the K-th score).
+
+    Any set of K rows that scores at least as well as every row left out is an exact
+    K-NN; the recall of a retrieved set S (K distinct rows, given by their exact
+    scores) is its best overlap with such a set, divided by K.  With s_K the K-th best
+    exact score and B the rows strictly better than s_K (all of them are among the
+    exact top K), every exact K-NN is B plus K - |B| of the rows tied at s_K, so the
+    best overlap is |S among B| + min(|S tied at s_K|, K - |B|).
+    ``exact_scores``: the exact top-K scores of each query, best first (M x K)."""
     rs = np.asarray(retrieved_scores, np.float64)
-    kb = np.asarray(kth_best, np.float64)[:, None]
-    ok = (rs <= kb) if minimize else (rs >= kb)
-    return ok.mean(axis=1)
+    ex = np.asarray(exact_scores, np.float64)
+    K = ex.shape[1]
+    sK = ex[:, K - 1:K]
+    strictly = (lambda a: a < sK) if minimize else (lambda a: a > sK)
+    n_b = strictly(ex).sum(axis=1)
+    hit_b = strictly(rs).sum(axis=1)
+    hit_tie = (rs == sK).sum(axis=1)
+    return (hit_b + np.minimum(hit_tie, K - n_b)) / K
 
 
 # ----------------------------------------------------------------------------------------

@@ -133,9 +133,11 @@ static void sort_pairs(or_pair* p, int64_t n, int minimize) {
 }
 
 /* Algorithm 1 on one row of scores s[0..N): for every bin, the best score, its
- * row, and the best score among the other rows of the bin (the runner-up, used
- * by the tests to decide whether a bin's winner is separated from the rest by
- * more than the rounding bound). */
+ * row and magnitude; and, for the tests' tolerance, the best score among the
+ * bin's other rows (V2) and the largest magnitude among those other rows (V2M).
+ * A winner that is ahead of V2 by more than the rounding bound of its own
+ * magnitude plus V2M is then ahead of every other row of the bin by more than
+ * the bound of the two scores, whatever their individual magnitudes. */
 static void partial_reduce_row(const double* s, const double* mag, int64_t N, int64_t L, int minimize,
                                double* V, int64_t* A, double* VM, double* V2, double* V2M) {
   const double worst = minimize ? INFINITY : -INFINITY;
@@ -147,14 +149,16 @@ static void partial_reduce_row(const double* s, const double* mag, int64_t N, in
       double y = s[j];
       double m = mag ? mag[j] : 0.0;
       if (better(y, v, minimize)) { /* the compare and the two conditional moves */
-        v2 = v;                       /* the old winner is now the best non-winner */
-        v2m = vm;
+        if (a >= 0) {                 /* the old winner joins the other rows */
+          v2 = v;                     /* it was at least as good as all of them */
+          if (vm > v2m) v2m = vm;
+        }
         v = y;
         vm = m;
         a = j;
-      } else if (better(y, v2, minimize) || (y == v2 && m > v2m)) {
-        v2 = y;                       /* row j can never win later: it is a non-winner */
-        v2m = m;
+      } else {                        /* row j is not the winner at this point, nor later */
+        if (better(y, v2, minimize)) v2 = y;
+        if (m > v2m) v2m = m;
       }
     }
     V[b] = v;

@@ -5,9 +5,11 @@ bound): e = gamma_n * mag, gamma_n = n u / (1 - n u), n = Dpad + 3, with u = 2^-
 (twice the unit roundoff of round-to-nearest, to cover matrix-unit adders that
 may truncate) and mag = sum_k |q_k x_k| (+ |x|^2/2 for L2, + 1 for cosine).
 
-  * bins: where the FP64 gap between a bin's winner and runner-up exceeds
-    e_w + e_r the GPU row must equal the oracle's; otherwise any row of the bin
-    whose FP64 score is within e_w + e_r of the winner is accepted;
+  * bins: where the FP64 gap between a bin's winner and the best of its other rows
+    exceeds e_w + e_r (e_r from the largest magnitude among the other rows, so the
+    winner is then ahead of every other row by more than the bound of the pair) the
+    GPU row must equal the oracle's; otherwise any row of the bin whose FP64 score is
+    within e_w + e_r of the winner is accepted;
   * values: |V_gpu - s64(row)| <= max(1e-5 |s64|, e(row)), s64 the FP64 score of
     the row the GPU returned;
   * top-K: every row the oracle ranks better than its K-th value by more than

@@ -5,6 +5,7 @@ pins it: brute force, a library routine, an exact enumeration, or an identity.
 """
 import itertools
 import math
+import struct
 from fractions import Fraction
 
 import numpy as np
@@ -314,13 +315,244 @@ def test_fp8_row_exponent_minimal():
     assert e[-1] == 0 and e[-5] == 0 and e[-3] == 1 and e[-2] == -8
 
 
-def test_normalize_rows_f32():
+def _f32(v: float) -> float:
+    """Round a Python float (FP64) to the nearest FP32 value, ties to even."""
+    return struct.unpack("<f", struct.pack("<f", v))[0]
+
+
+def _normalize_row_scalar(row):
+    """One row unit-normalised with scalar FP32 steps, written independently of the
+    oracle: Python FP64 arithmetic with a rounding to FP32 after every product, sum,
+    square root and division.  (Each of these FP64 results rounded once more to FP32
+    is the correctly rounded FP32 result: FP64 carries more than 2 * 24 + 2 bits.)"""
+    acc = 0.0
+    for v in row:
+        acc = _f32(acc + _f32(float(v) * float(v)))
+    nrm = _f32(math.sqrt(acc))
+    if nrm == 0.0:
+        return [0.0] * len(row)
+    return [_f32(float(v) / nrm) for v in row]
+
+
+def test_normalize_rows_f32_bit_exact_vs_scalar_loop():
+    """Cosine preparation (Sec. 2, cosine similarity as MIPS on normalised rows): the
+    oracle's vectorised FP32 normalisation equals, bit for bit, a scalar loop that rounds
+    to FP32 after every operation in increasing dimension order, on rows of ordinary,
+    tiny, huge and mixed magnitudes, single-entry rows and a zero row; and every
+    non-zero result has unit FP64 norm within the FP32 rounding of D + 2 steps."""
     rng = np.random.default_rng(12)
-    X = rng.standard_normal((100, 100)).astype(np.float32)
+    X = rng.standard_normal((64, 100)).astype(np.float32)
     X[3] = 0
+    X[4] = 0
+    X[4, 17] = -3.5
+    X[5] *= np.float32(1e-18)
+    X[6] *= np.float32(1e17)
+    X[7] = (rng.standard_normal(100) * 10.0 ** rng.uniform(-6, 6, 100)).astype(np.float32)
+    X[8, :50] = 1.0
     Xn = oracle.normalize_rows_f32(X)
+    ref = np.array([_normalize_row_scalar(r) for r in X], np.float32)
+    np.testing.assert_array_equal(Xn.view(np.uint32), ref.view(np.uint32))
     n = np.sqrt((Xn.astype(np.float64) ** 2).sum(1))
-    assert np.all(np.abs(n[np.arange(100) != 3] - 1) < 1e-6) and n[3] == 0
+    nz = np.abs(X).max(1) > 0
+    assert np.all(np.abs(n[nz] - 1) < (100 + 2) * 2.0 ** -24 * 2) and np.all(n[~nz] == 0)
+
+
+# ---------------------------------------------------------------- rounding magnitudes
+def _emulated_f32_scores(Q, X, metric, order):
+    """FP32 evaluation of the scores the way a matrix unit may sum them: products rounded
+    to FP32, then summed in FP32 in the given order of dimensions ("seq", "rev" or
+    "pairs"); L2 starts from -|x|^2/2 summed in FP32; cosine normalises both sides in
+    FP32 first.  Returns an M x N FP64 array holding the FP32 results."""
+    Q = np.asarray(Q, np.float32)
+    X = np.asarray(X, np.float32)
+    if metric == "cosine":
+        Q, X = oracle.normalize_rows_f32(Q), oracle.normalize_rows_f32(X)
+    P = Q[:, None, :] * X[None, :, :]  # FP32 products, correctly rounded
+    D = P.shape[2]
+    if metric == "l2":
+        h = np.zeros(X.shape[0], np.float32)
+        for d in range(D):
+            h = h + X[:, d] * X[:, d]
+        acc = np.broadcast_to(-(h * np.float32(0.5)), P.shape[:2]).astype(np.float32)
+    else:
+        acc = np.zeros(P.shape[:2], np.float32)
+    if order == "pairs":
+        T = P
+        while T.shape[2] > 1:
+            if T.shape[2] % 2:
+                T = np.concatenate([T, np.zeros(T.shape[:2] + (1,), np.float32)], axis=2)
+            T = T[:, :, 0::2] + T[:, :, 1::2]
+        acc = acc + T[:, :, 0]
+    else:
+        for d in (range(D) if order == "seq" else range(D - 1, -1, -1)):
+            acc = acc + P[:, :, d]
+    s = acc.astype(np.float64)
+    return -s if metric == "l2" else s  # the accumulator holds <q,x> - |x|^2/2
+
+
+def _gamma(n, u=2.0 ** -24):
+    return n * u / (1 - n * u)
+
+
+@pytest.mark.parametrize("metric", ["mips", "l2", "cosine"])
+def test_magnitudes_bound_fp32_rounding(metric):
+    """The parity rule's rounding bound e = gamma_n * mag with n = D + 3 (Higham's bound
+    for a sum of products in any order) holds for FP32 evaluations of the score in three
+    summation orders, at the round-to-nearest unit 2^-24 (the tests use twice that).  For
+    L2 the data make the rounding of |x|^2/2 dominate: the error is far above
+    gamma_n * sum|q_k x_k|, so a magnitude without the 1/2 |x|^2 term fails here."""
+    rng = np.random.default_rng(21)
+    D = 96
+    if metric == "l2":
+        Q = (rng.standard_normal((24, D)) * 1e-3).astype(np.float32)
+        X = (rng.standard_normal((200, D)) * 100.0).astype(np.float32)
+    else:
+        Q = rng.standard_normal((24, D)).astype(np.float32)
+        X = (rng.standard_normal((200, D)) * np.exp(rng.uniform(-2, 2, (200, 1)))).astype(np.float32)
+    S, MAG = oracle.scores(Q, X, metric)
+    g = _gamma(D + 3)
+    worst = 0.0
+    for order in ("seq", "rev", "pairs"):
+        err = np.abs(_emulated_f32_scores(Q, X, metric, order) - S)
+        assert np.all(err <= g * MAG), (order, float(np.max(err / (g * MAG))))
+        worst = max(worst, float(np.max(err / (g * MAG))))
+    assert worst > 1e-3  # the comparison is not vacuous
+    if metric == "l2":
+        dot_mag = np.abs(Q.astype(np.float64)) @ np.abs(X.astype(np.float64)).T
+        err = np.abs(_emulated_f32_scores(Q, X, metric, "seq") - S)
+        assert np.max(err / (g * dot_mag)) > 10.0
+
+
+def test_magnitudes_equality_cases_and_invariances():
+    """Magnitudes: never below |score| (MIPS, L2) or |score| + 1 (cosine); equal to them
+    when no cancellation can occur (MIPS and cosine on non-negative data, L2 with
+    non-positive queries against non-negative rows, L2 with a zero query: 1/2 |x|^2);
+    unchanged when a query changes sign; MIPS magnitudes scale with the query; cosine
+    magnitudes are scale-free; a zero-norm cosine pair has score 0 and magnitude 1."""
+    rng = np.random.default_rng(22)
+    Qp = rng.integers(0, 9, (5, 12)).astype(np.float32)
+    Xp = rng.integers(0, 9, (30, 12)).astype(np.float32)
+    Qp[0, 0] = 1.0
+    Xp[:, 1] = 1.0  # no zero rows
+    Qp[:, 1] = 1.0
+    Qr = rng.standard_normal((5, 12)).astype(np.float32)
+    Xr = rng.standard_normal((30, 12)).astype(np.float32)
+    for metric in ("mips", "l2", "cosine"):
+        S, MAG = oracle.scores(Qr, Xr, metric)
+        extra = 1.0 if metric == "cosine" else 0.0
+        assert np.all(MAG >= np.abs(S) + extra - 1e-12)
+        S2, MAG2 = oracle.scores(-Qr, Xr, metric)
+        np.testing.assert_allclose(MAG2, MAG, rtol=1e-14)
+    S, MAG = oracle.scores(Qp, Xp, "mips")
+    np.testing.assert_array_equal(MAG, S)
+    S, MAG = oracle.scores(-Qp, Xp, "l2")
+    np.testing.assert_array_equal(MAG, S)
+    S, MAG = oracle.scores(np.zeros_like(Qp), Xp, "l2")
+    np.testing.assert_array_equal(MAG, S)
+    np.testing.assert_array_equal(S, 0.5 * (Xp.astype(np.float64) ** 2).sum(1)[None, :].repeat(5, 0))
+    S, MAG = oracle.scores(Qp, Xp, "cosine")
+    np.testing.assert_allclose(MAG, S + 1.0, rtol=1e-14)
+    _, M1 = oracle.scores(Qr, Xr, "mips")
+    _, M4 = oracle.scores(Qr * np.float32(4), Xr, "mips")
+    np.testing.assert_array_equal(M4, 4 * M1)
+    _, C1 = oracle.scores(Qr, Xr, "cosine")
+    _, C2 = oracle.scores(Qr * np.float32(4), Xr * np.float32(0.5), "cosine")
+    np.testing.assert_allclose(C2, C1, rtol=1e-14)
+    Xz = Xr.copy()
+    Xz[7] = 0
+    S, MAG = oracle.scores(Qr, Xz, "cosine")
+    assert np.all(S[:, 7] == 0.0) and np.all(MAG[:, 7] == 1.0)
+
+
+@pytest.mark.parametrize("metric", ["mips", "l2", "cosine"])
+def test_bin_magnitudes_vs_bruteforce(metric):
+    """Per bin the search reports the winner's magnitude (bin_mag) and, over the bin's
+    other rows, the best score (bin2_v) and the largest magnitude (bin2_mag), against a
+    brute-force scan of the full score and magnitude matrices on tie-rich inputs, for
+    every bin count; a bin of one row has no other rows (worst score, magnitude 0)."""
+    rng = np.random.default_rng(23)
+    Q = rng.integers(-2, 3, size=(4, 5)).astype(np.float32)
+    X = rng.integers(-2, 3, size=(23, 5)).astype(np.float32)
+    S, MAG = oracle.scores(Q, X, metric)
+    mn = oracle.minimize_for(metric)
+    worst_v = np.inf if mn else -np.inf
+    for L in range(1, 24):
+        r = oracle.search(Q, X, metric, L, 1, bins=True)
+        for i in range(4):
+            for b in range(L):
+                j0, j1 = oracle.bin_start(b, 23, L), oracle.bin_start(b + 1, 23, L)
+                a = r["bin_i"][i, b]
+                assert r["bin_mag"][i, b] == MAG[i, a]
+                others = [j for j in range(j0, j1) if j != a]
+                if others:
+                    sv = S[i, others]
+                    assert r["bin2_v"][i, b] == (sv.min() if mn else sv.max())
+                    assert r["bin2_mag"][i, b] == MAG[i, others].max()
+                else:
+                    assert r["bin2_v"][i, b] == worst_v and r["bin2_mag"][i, b] == 0.0
+
+
+# ---------------------------------------------------------------- tie-aware recall (eq. recall-def)
+def _recall_by_enumeration(scores, S, K, minimize):
+    """Best overlap of the retrieved rows S with any exact K-NN set: every K-subset T of
+    the rows none of whose members is beaten by a row outside it."""
+    n = len(scores)
+    best = 0
+    for T in itertools.combinations(range(n), K):
+        inside = [scores[j] for j in T]
+        outside = [scores[j] for j in range(n) if j not in T]
+        if outside and (max(inside) > min(outside) if minimize else min(inside) < max(outside)):
+            continue
+        best = max(best, len(set(T) & set(S)))
+    return Fraction(best, K)
+
+
+def _exact_topk_scores(scores, K, minimize):
+    return sorted(scores, reverse=not minimize)[:K]
+
+
+@pytest.mark.parametrize("scores,K,S,minimize,expect", [
+    ([6, 5, 5, 5], 2, [1, 2], False, Fraction(1, 2)),   # two tied rows cannot replace the strictly better one
+    ([6, 5, 5, 5], 2, [0, 3], False, Fraction(1)),      # any one of the tied rows completes the set
+    ([1, 2, 2, 2], 2, [1, 2], True, Fraction(1, 2)),    # the same, minimising
+    ([1, 2, 2, 2], 2, [3, 0], True, Fraction(1)),
+    ([4, 3, 2, 1], 2, [0, 2], False, Fraction(1, 2)),   # no ties: strict recall
+    ([7, 7, 7], 2, [2, 0], False, Fraction(1)),         # all tied: every set is exact
+    ([3, 9, 9, 1, 9], 3, [1, 3, 4], False, Fraction(2, 3)),
+    ([3, 9, 9, 1, 9], 1, [0], False, Fraction(0)),
+])
+def test_recall_tie_aware_hand_worked(scores, K, S, minimize, expect):
+    """Hand-worked cases of recall with ties in both directions, and the enumeration
+    agrees with them."""
+    ex = np.array([_exact_topk_scores(scores, K, minimize)], np.float64)
+    rs = np.array([[scores[j] for j in S]], np.float64)
+    got = oracle.recall_tie_aware(rs, ex, minimize)[0]
+    assert got == float(expect)
+    assert _recall_by_enumeration(scores, S, K, minimize) == expect
+
+
+@pytest.mark.parametrize("minimize", [False, True])
+def test_recall_tie_aware_vs_enumeration(minimize):
+    """The closed form (strictly better retrieved rows + the tied ones that fit) equals the
+    best overlap with any exact K-NN set, by enumeration, on small-integer scores full of
+    ties, for every K and many retrieved sets; without ties it is the strict recall."""
+    rng = np.random.default_rng(24)
+    for n in range(1, 9):
+        for trial in range(12):
+            scores = rng.integers(0, 4, n).tolist()
+            for K in range(1, n + 1):
+                ex = np.array([_exact_topk_scores(scores, K, minimize)], np.float64)
+                for _ in range(4):
+                    S = rng.choice(n, K, replace=False).tolist()
+                    rs = np.array([[scores[j] for j in S]], np.float64)
+                    got = oracle.recall_tie_aware(rs, ex, minimize)[0]
+                    assert got == float(_recall_by_enumeration(scores, S, K, minimize)), (scores, K, S)
+    scores = rng.permutation(50).astype(np.float64)
+    truth = np.argsort(scores if minimize else -scores)[:7]
+    for _ in range(20):
+        S = rng.choice(50, 7, replace=False)
+        got = oracle.recall_tie_aware(scores[S][None], scores[truth][None], minimize)[0]
+        assert got == oracle.recall(S[None], truth[None])[0]
 
 
 # ---------------------------------------------------------------- backward reference
