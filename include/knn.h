@@ -20,11 +20,20 @@
  * Expected recall (Sec. 5.1, eq. recall) is at least ((L-1)/L)^(K-1).
  *
  * Conventions for every entry point:
- *   - Pointers named Q, X, out_*, bins_*, g, idx, dQ, dX are DEVICE pointers,
- *     owned by the caller, row-major and contiguous.  FP32 data is 4-byte aligned,
- *     BF16 data 2-byte aligned.  Handles (knn_db, knn_plan) are owned by the library.
+ *   - Pointers named Q, X, out_*, bins_*, g, idx, dQ, dX, buf, workspace are DEVICE
+ *     pointers, owned by the caller, row-major and contiguous.  FP32 data is 4-byte
+ *     aligned, BF16 data 2-byte aligned, buf and workspace 16-byte aligned.
+ *   - Device memory is the caller's: the library allocates none, except knn_search
+ *     (the plain form, which takes raw rows and prepares them on every call).  Each call
+ *     that needs memory beyond its inputs and outputs takes a `workspace` of at least the
+ *     size its *_workspace_size query reports, and a prepared database lives in a buffer
+ *     of knn_db_prepare_size bytes.  The handles knn_db and knn_plan are small host
+ *     objects owned by the library; they point into that caller memory, which must stay
+ *     valid and unchanged for their lifetime.  A workspace holds nothing between calls;
+ *     calls that share one must not overlap in time (order them on one stream).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it
- *     and the call returns without synchronising, except where noted.
+ *     and the call returns without synchronising, except where noted; the calls that do
+ *     not synchronise may be captured into a hipGraph.
  *   - Arguments are checked before anything is enqueued.  On error the call returns
  *     a non-zero knn_status, knn_last_error() describes it (per thread), nothing is
  *     enqueued and the outputs are untouched.  No C++ exception crosses the ABI.
@@ -84,20 +93,29 @@ int32_t knn_device_count(void);
 
 /* ------------------------------------------------------------------ database preparation */
 
-/* Prepare a database once for many searches (the paper passes the L2 half norms
- * precomputed, appendix on Euclidean search): for cosine the rows are
- * unit-normalised in FP32; rows are then converted to `compute` (FP32 copy, BF16
- * round-to-nearest-even, or per-row scaled FP8 E4M3), zero-padded to the MFMA
- * depth and stored in the layout the distance kernel streams; L2 also stores
- * |x~|^2 / 2 of the converted rows.  For the FP32 rerank of low-precision
- * searches the handle keeps X's device pointer: X must stay valid and unchanged
- * for the life of the handle.
- *   X        device, N x D, type in_dtype (KNN_F32 or KNN_BF16)
- *   out      receives the handle; free it with knn_db_destroy.
- * Allocates device memory (hipMalloc); synchronises `stream` before returning. */
-knn_status knn_db_create(const void* X, int32_t in_dtype, int64_t N, int32_t D, int32_t metric,
-                         int32_t compute, void* stream, knn_db** out);
+/* Bytes of device memory a prepared database of N rows of depth D takes (the rows
+ * converted to `compute` and laid out in tiles, plus the original rows' half norms for
+ * L2 or inverse norms for cosine).  0 for invalid arguments. */
+size_t knn_db_prepare_size(int64_t N, int32_t D, int32_t metric, int32_t compute);
 
+/* Prepare a database once for many searches, into the caller's buffer.  The paper
+ * passes the L2 half norms precomputed (appendix on Euclidean search) and pads the depth
+ * to the matrix unit's (100 -> 128 in its benchmark appendix); this call does both:
+ * for cosine the rows are unit-normalised in FP32; rows are then converted to `compute`
+ * (FP32 copy, BF16 round-to-nearest-even, or per-row scaled FP8 E4M3), zero-padded to
+ * the MFMA depth and stored in the layout the distance kernel streams; L2 also stores
+ * |x~|^2 / 2 of the converted rows.
+ *   X        device, N x D, type in_dtype (KNN_F32 or KNN_BF16).  The handle keeps X's
+ *            pointer for the FP32 rerank of low-precision searches: X must stay valid
+ *            and unchanged for the life of the handle.
+ *   buf      device, at least knn_db_prepare_size(N, D, metric, compute) bytes; holds
+ *            the prepared database for the life of the handle
+ *   out      receives the handle (a host object); release it with knn_db_destroy.
+ * Enqueues one kernel on `stream`; no allocation of device memory, no synchronisation. */
+knn_status knn_db_prepare(const void* X, int32_t in_dtype, int64_t N, int32_t D, int32_t metric, int32_t compute,
+                          void* buf, size_t bytes, void* stream, knn_db** out);
+
+/* Release the handle (not the caller's buffer). */
 knn_status knn_db_destroy(knn_db* db);
 
 /* Copy the prepared rows back to HOST buffers in plain row-major form, for tests:
@@ -110,30 +128,45 @@ knn_status knn_db_export(const knn_db* db, void* codes, int32_t* exponents, floa
 
 /* ------------------------------------------------------------------ search */
 
-/* The plain FP32 search: Q (M x D) against X (N x D), both FP32 device arrays.
+/* The plain FP32 search (Sec. 2 eq. 1-2; Sec. 5: PartialReduce, Algorithm 1, then the
+ * exact top-K of the bin winners): Q (M x D) against X (N x D), both FP32 device arrays.
  * L <= 0 chooses L = knn_bins_for_recall(K, 0.95, N).  Writes the best K per query,
- * best first: out_val FP32[M x K], out_idx int32[M x K].  Allocates its temporary
- * buffers stream-ordered and prepares X on every call.  Stream-ordered temporaries
- * (here and in the other search calls) come from a memory pool the library creates
- * per device, which keeps freed memory for later calls until the process ends. */
+ * best first: out_val FP32[M x K], out_idx int32[M x K].  Being the form that takes raw
+ * rows, it prepares X on every call into a stream-ordered temporary from a memory pool
+ * the library keeps per device (freed memory is kept for later calls until the process
+ * ends); knn_db_prepare + knn_db_search is the allocation-free form. */
 knn_status knn_search(const float* Q, int64_t M, const float* X, int64_t N, int32_t D, int32_t K,
                       int64_t L, int32_t metric, float* out_val, int32_t* out_idx, void* stream);
 
-/* Search a prepared database.
+/* Search a prepared database with the options of the paper's op (App. A.1).
  *   Q          device, M x D, type q_dtype (KNN_F32 or KNN_BF16)
- *   L          bins (L <= 0: knn_bins_for_recall(K, 0.95, N))
+ *   L          bins; L <= 0 derives it from recall_target (<= 0: 0.95) by eq. l:approx
+ *              (Sec. 5.1) for input_size_override rows if that is > 0, else for the
+ *              database's N rows, keeping that bin density on these rows, as
+ *              knn_approx_bins does: a database that is one bin-aligned shard of a
+ *              longer one then gets exactly the longer one's bins (the override's use
+ *              in a distributed search, App. A.1)
  *   rerank_k   0: return the top-K of the bin winners by the compute-type score;
- *              K..L: take the best rerank_k bin winners by the compute-type score,
- *              rescore them in FP32 from the original Q and X rows, return the best K
- *              (the precision form of the search: BF16 / FP8 GEMM + FP32 rerank)
+ *              K..min(L, 1024): take the best rerank_k bin winners by the compute-type
+ *              score, rescore them in FP32 from the original Q and X rows, return the
+ *              best K (the precision form of the search: BF16 / FP8 GEMM + FP32 rerank)
  *   out_val/out_idx  M x K, best first (scores are FP32 rescored ones when reranking)
  *   bins_val/bins_idx optional M x L bin winners (Algorithm 1's V and A, compute-type
  *              scores in the metric's own sign); NULL to skip (the `aggregate_to_topk`
- *              option of the paper's op corresponds to out_* being used).
- * Temporary buffers are allocated stream-ordered. */
+ *              option of the paper's op corresponds to out_* being used)
+ *   workspace  device, >= the size knn_db_search_workspace_size reports for the same
+ *              arguments (NULL allowed when that is 0)
+ * No allocation, no synchronisation: may be captured into a hipGraph. */
 knn_status knn_db_search(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, int32_t K, int64_t L,
-                         int32_t rerank_k, float* out_val, int32_t* out_idx, float* bins_val,
-                         int32_t* bins_idx, void* stream);
+                         double recall_target, int64_t input_size_override, int32_t rerank_k, float* out_val,
+                         int32_t* out_idx, float* bins_val, int32_t* bins_idx, void* workspace, size_t ws_bytes,
+                         void* stream);
+
+/* Workspace bytes knn_db_search needs for these arguments (with_bins: bins_val and
+ * bins_idx will be given).  Host only. */
+knn_status knn_db_search_workspace_size(const knn_db* db, int64_t M, int32_t K, int64_t L, double recall_target,
+                                        int64_t input_size_override, int32_t rerank_k, int32_t with_bins,
+                                        size_t* bytes);
 
 /* The two steps of a search exposed on their own, for callers that reuse prepared
  * queries and for timing the distance kernel alone.
@@ -173,30 +206,41 @@ typedef struct {
   int32_t* out_idx;
 } knn_batch;
 
-/* Build a plan for `nb` uneven query batches against `ndb` prepared databases.
- * All buffers the search needs are allocated here, so knn_search_batched allocates
- * nothing and may be captured into a hipGraph.  The batch pointers are bound now:
- * replays read the queries from, and write the results to, the same buffers.
- * For each database the plan picks L >= knn_bins_for_recall(max K, recall_target, N)
- * (more bins than that when one bin's rows would not fit the 2 MiB that a group of
- * workgroups streams through an XCD's L2; more bins never lower the expected
- * recall) and the kernel tiling; with tune != 0 it times candidates on `stream`
- * with hipEvents (the autotuner) and caches the choice in the JSON file
- * `cache_path` (NULL: no cache); with tune == 0 it uses a fixed heuristic.
- * Synchronises `stream`. */
+/* Batched search (not in the paper: many uneven query batches against several
+ * databases in one persistent launch).  Three steps:
+ * knn_plan_create: host only.  Plans `nb` uneven query batches against `ndb` prepared
+ *   databases (BF16).  The batch pointers are bound now: every run reads the queries
+ *   from, and writes the results to, the same buffers.  For each database the plan picks
+ *   L >= knn_bins_for_recall(max K, recall_target, N) (more bins than that when one
+ *   bin's rows would not fit the 2 MiB that a group of workgroups streams through an
+ *   XCD's L2; more bins never lower the expected recall) and the kernel tiling by a fixed
+ *   heuristic, or with tune != 0 by timing candidates in knn_plan_setup (the autotuner),
+ *   taking earlier choices from the JSON cache file `cache_path` (NULL: no cache) when
+ *   they were made for the same device, database shape, batch sizes, K and recall bound
+ *   and are valid for this plan.
+ * knn_plan_workspace_size: host only; the device bytes knn_plan_setup needs (covering
+ *   every choice the autotuner may try).
+ * knn_plan_setup: lays the plan out in the caller's workspace (prepared queries, bins,
+ *   the device work list), runs the autotuner if requested (it times candidates on
+ *   `stream` with hipEvents and writes the cache) and uploads the work list.
+ *   Synchronises `stream`.  The workspace must stay valid for the life of the plan. */
 knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn_batch* batches, int32_t nb,
                            int32_t q_dtype, double recall_target, int32_t tune, const char* cache_path,
-                           void* stream, knn_plan** out);
+                           knn_plan** out);
+knn_status knn_plan_workspace_size(const knn_plan* plan, size_t* bytes);
+knn_status knn_plan_setup(knn_plan* plan, void* workspace, size_t ws_bytes, void* stream);
 
 /* Run every batch of the plan: one query-preparation launch, one persistent
  * distance + bin-reduce launch over a device work list that covers all batches
- * and databases, and one top-K launch.  No allocation, no host synchronisation. */
+ * and databases, and one top-K launch.  No allocation, no host synchronisation: may be
+ * captured into a hipGraph.  KNN_ERR_INVALID before knn_plan_setup. */
 knn_status knn_search_batched(knn_plan* plan, void* stream);
 
 /* The plan's per-database choices: L, query-block width and rows per work item
  * (host arrays of length ndb; any may be NULL). */
 knn_status knn_plan_info(const knn_plan* plan, int64_t* L, int32_t* qblock, int64_t* chunk_rows);
 
+/* Release the plan (not the caller's workspace). */
 knn_status knn_plan_destroy(knn_plan* plan);
 
 /* ------------------------------------------------------------------ approx_max_k on scores */
@@ -233,12 +277,19 @@ int64_t knn_approx_bins(int64_t n, int32_t K, double recall_target, int64_t inpu
  *                  for reduction_dim 1, R x B row-major for reduction_dim 0.  Indices
  *                  are positions along the reduced dimension; values are the scores
  *                  widened to FP32 (a -0 score may come back as +0).
- * Bit-exact: no arithmetic is done on the scores.  B = 0 is a no-op.  With
- * aggregate_to_topk the B x L bins are a stream-ordered temporary (hipMallocAsync). */
+ *   workspace      device, >= the size knn_approx_workspace_size reports (the bins of
+ *                  every slice when aggregating, else 0 and NULL allowed)
+ * Bit-exact: no arithmetic is done on the scores.  B = 0 is a no-op.  No allocation, no
+ * synchronisation. */
 knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_t rows, int64_t cols, int64_t ld,
                             int32_t reduction_dim, int32_t K, double recall_target, int64_t input_size_override,
                             int64_t L, int32_t minimize, int32_t aggregate_to_topk, float* out_val,
-                            int32_t* out_idx, void* stream);
+                            int32_t* out_idx, void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of knn_approx_top_k for the same arguments (host only). */
+knn_status knn_approx_workspace_size(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int32_t reduction_dim,
+                                     int32_t K, double recall_target, int64_t input_size_override, int64_t L,
+                                     int32_t minimize, int32_t aggregate_to_topk, size_t* bytes);
 
 /* ------------------------------------------------------------------ backward */
 

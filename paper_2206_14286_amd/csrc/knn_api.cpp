@@ -157,6 +157,8 @@ struct DevBuf {  // stream-ordered temporary from the library pool
 }  // namespace
 
 // --------------------------------------------------------------------------- handles
+// A prepared database lives in caller memory (knn_db_prepare); the handle is a host
+// object that only points into it.
 struct knn_db {
   int32_t in_dt, compute, metric, D, dpad, ng;
   int64_t N, n_tiles;
@@ -166,11 +168,12 @@ struct knn_db {
   const void* X = nullptr;          // caller's rows (not owned)
 };
 
-struct GroupPlan {
+struct GroupPlan {  // all batches against one database
   int32_t db;
   int64_t M = 0, L = 0, L_min = 0, bins_per_chunk = 0, n_qb = 0, n_chunks = 0, q_tiles_n = 0;
   int32_t ncb = 1, K_max = 1;
-  unsigned char* q_tiles = nullptr;
+  bool tune = false;  // still to be tuned in knn_plan_setup
+  unsigned char* q_tiles = nullptr;  // inside the bound workspace
   float* binV = nullptr;
   int32_t* binA = nullptr;
 };
@@ -180,12 +183,21 @@ struct knn_plan {
   std::vector<knn_batch> batches;
   std::vector<GroupPlan> groups;
   int32_t q_dtype = KNN_F32, compute = KNN_BF16;
+  std::string cache_path;
   int64_t total_q_rows = 0, n_items = 0, n_sel_rows = 0;
   int n_blocks = 0, max_ng = 0, n_segs = 0, max_K = 1, lds_bytes = 0;
+  bool bound = false;  // knn_plan_setup succeeded
+  // descriptors: built on the host, uploaded into the workspace
+  std::vector<QSeg> segs;
+  std::vector<GroupDesc> gds;
+  std::vector<WorkItem> items;
+  std::vector<SelRow> sel;
   QSeg* d_segs = nullptr;
   GroupDesc* d_groups = nullptr;
   WorkItem* d_items = nullptr;
   SelRow* d_sel = nullptr;
+  float* tune_val = nullptr;  // autotuner's top-K output
+  int32_t* tune_idx = nullptr;
 };
 
 // --------------------------------------------------------------------------- helpers
@@ -234,18 +246,56 @@ extern "C" int32_t knn_device_count(void) {
 }
 
 // --------------------------------------------------------------------------- database
-extern "C" knn_status knn_db_create(const void* X, int32_t in_dtype, int64_t N, int32_t D, int32_t metric,
-                                    int32_t compute, void* stream, knn_db** out) {
-  g_last_error.clear();
-  if (!out) return fail(KNN_ERR_INVALID, "out is NULL");
-  if (!X) return fail(KNN_ERR_INVALID, "X is NULL");
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Caller memory of a prepared database: the tiles, then (L2 / cosine) one float per
+// row of the original rows' half norms / inverse norms.
+struct DbLayout {
+  size_t tiles = 0, aux = 0, total = 0;
+};
+
+DbLayout db_layout(int64_t N, int32_t D, int32_t metric, int32_t compute) {
+  DbLayout l;
+  const int ng = groups_for(dpad_for(D, compute), compute);
+  l.tiles = 0;
+  l.aux = align_up((size_t)(ceil_div(N, kTileRows) * tile_bytes(ng)));
+  l.total = l.aux + (metric == KNN_MIPS ? 0 : align_up(sizeof(float) * (size_t)N));
+  return l;
+}
+
+knn_status check_db_args(int32_t in_dtype, int64_t N, int32_t D, int32_t metric, int32_t compute) {
   if (!valid_in(in_dtype)) return fail(KNN_ERR_INVALID, "in_dtype must be KNN_F32 or KNN_BF16");
   if (!valid_compute(compute)) return fail(KNN_ERR_INVALID, "bad compute dtype %d", compute);
   if (!valid_metric(metric)) return fail(KNN_ERR_INVALID, "bad metric %d", metric);
   if (N < 1 || N > kMaxRows) return fail(KNN_ERR_INVALID, "N must be in [1, 2^31 - 64]");
   if (D < 1) return fail(KNN_ERR_INVALID, "D must be >= 1");
   if (D > kMaxDpad) return fail(KNN_ERR_UNSUPPORTED, "D must be <= %d", kMaxDpad);
-  hipStream_t s = (hipStream_t)stream;
+  return KNN_OK;
+}
+
+}  // namespace
+
+extern "C" size_t knn_db_prepare_size(int64_t N, int32_t D, int32_t metric, int32_t compute) {
+  if (check_db_args(KNN_F32, N, D, metric, compute) != KNN_OK) return 0;
+  return db_layout(N, D, metric, compute).total;
+}
+
+extern "C" knn_status knn_db_prepare(const void* X, int32_t in_dtype, int64_t N, int32_t D, int32_t metric,
+                                     int32_t compute, void* buf, size_t bytes, void* stream, knn_db** out) {
+  g_last_error.clear();
+  if (!out) return fail(KNN_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  knn_status st = check_db_args(in_dtype, N, D, metric, compute);
+  if (st != KNN_OK) return st;
+  if (!X) return fail(KNN_ERR_INVALID, "X is NULL");
+  if (!buf) return fail(KNN_ERR_INVALID, "buf is NULL");
+  if (reinterpret_cast<uintptr_t>(buf) % 16 != 0) return fail(KNN_ERR_INVALID, "buf must be 16-byte aligned");
+  const DbLayout lay = db_layout(N, D, metric, compute);
+  if (bytes < lay.total)
+    return fail(KNN_ERR_INVALID, "buf too small (%zu < %zu bytes, see knn_db_prepare_size)", bytes, lay.total);
   auto* db = new (std::nothrow) knn_db();
   if (!db) return fail(KNN_ERR_OOM, "host allocation");
   db->in_dt = in_dtype;
@@ -257,18 +307,14 @@ extern "C" knn_status knn_db_create(const void* X, int32_t in_dtype, int64_t N, 
   db->N = N;
   db->n_tiles = ceil_div(N, kTileRows);
   db->X = X;
-  hipError_t e = hipMalloc(&db->tiles, (size_t)(db->n_tiles * tile_bytes(db->ng)));
-  if (e == hipSuccess && metric == KNN_L2) e = hipMalloc(&db->orig_half_norm, sizeof(float) * (size_t)N);
-  if (e == hipSuccess && metric == KNN_COSINE) e = hipMalloc(&db->orig_rnorm, sizeof(float) * (size_t)N);
+  unsigned char* base = static_cast<unsigned char*>(buf);
+  db->tiles = base + lay.tiles;
+  if (metric == KNN_L2) db->orig_half_norm = reinterpret_cast<float*>(base + lay.aux);
+  if (metric == KNN_COSINE) db->orig_rnorm = reinterpret_cast<float*>(base + lay.aux);
+  const hipError_t e = launch_prepare(X, in_dtype, N, D, metric, compute, true, db->tiles, db->n_tiles,
+                                      db->orig_half_norm, db->orig_rnorm, (hipStream_t)stream);
   if (e != hipSuccess) {
-    knn_db_destroy(db);
-    return fail(KNN_ERR_OOM, "hipMalloc for the prepared database: %s", hipGetErrorString(e));
-  }
-  e = launch_prepare(X, in_dtype, N, D, metric, compute, true, db->tiles, db->n_tiles, db->orig_half_norm,
-                     db->orig_rnorm, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) {
-    knn_db_destroy(db);
+    delete db;
     return hip_fail(e, "database preparation");
   }
   *out = db;
@@ -276,11 +322,7 @@ extern "C" knn_status knn_db_create(const void* X, int32_t in_dtype, int64_t N, 
 }
 
 extern "C" knn_status knn_db_destroy(knn_db* db) {
-  if (!db) return KNN_OK;
-  if (db->tiles) (void)hipFree(db->tiles);
-  if (db->orig_half_norm) (void)hipFree(db->orig_half_norm);
-  if (db->orig_rnorm) (void)hipFree(db->orig_rnorm);
-  delete db;
+  delete db;  // the prepared rows are the caller's memory
   return KNN_OK;
 }
 
@@ -315,73 +357,56 @@ extern "C" knn_status knn_db_export(const knn_db* db, void* codes, int32_t* expo
 }
 
 // --------------------------------------------------------------------------- search core
-static knn_status search_core(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, int32_t K, int64_t L,
-                              int32_t rerank_k, float* out_val, int32_t* out_idx, float* bins_val,
-                              int32_t* bins_idx, hipStream_t s) {
-  if (M == 0) return KNN_OK;
-  const int dt = db->compute, ng = db->ng;
-  const int ncb = pick_ncb(dt, ng, M);
-  const int64_t QB = (int64_t)kWaves * 32 * ncb;
-  const int64_t n_qb = ceil_div(M, QB);
-  const int64_t q_tiles_n = n_qb * QB / kTileRows;
-  const int64_t bpc = pick_bins_per_chunk(db->N, L, n_qb, db->ng);
-  const int64_t n_chunks = ceil_div(L, bpc);
+namespace {
 
-  DevBuf qbuf, vbuf, abuf, cbufv, cbufi;
-  HIP_TRY(qbuf.alloc((size_t)(q_tiles_n * tile_bytes(ng)), s), "hipMallocAsync (queries)");
-  float* binV = bins_val;
-  int32_t* binA = bins_idx;
-  if (!binV) {
-    HIP_TRY(vbuf.alloc(sizeof(float) * (size_t)(M * L), s), "hipMallocAsync (bins)");
-    binV = (float*)vbuf.p;
+// Workspace of one search: the prepared queries, the M x L bin winners (unless the
+// caller takes them), the rerank candidates.  Offsets are 256-byte aligned.
+struct SearchLayout {
+  int ncb = 1;
+  int64_t n_qb = 0, q_tiles_n = 0, bpc = 0, n_chunks = 0;
+  size_t q = 0, bv = 0, ba = 0, cv = 0, ci = 0, total = 0;
+};
+
+SearchLayout search_layout(const knn_db* db, int64_t M, int64_t L, int32_t rerank_k, bool bins_given) {
+  SearchLayout l;
+  if (M == 0) return l;
+  l.ncb = pick_ncb(db->compute, db->ng, M);
+  const int64_t QB = (int64_t)kWaves * 32 * l.ncb;
+  l.n_qb = ceil_div(M, QB);
+  l.q_tiles_n = l.n_qb * QB / kTileRows;
+  l.bpc = pick_bins_per_chunk(db->N, L, l.n_qb, db->ng);
+  l.n_chunks = ceil_div(L, l.bpc);
+  size_t off = 0;
+  l.q = off;
+  off += align_up((size_t)(l.q_tiles_n * tile_bytes(db->ng)));
+  if (!bins_given) {
+    l.bv = off;
+    off += align_up(sizeof(float) * (size_t)(M * L));
+    l.ba = off;
+    off += align_up(sizeof(int32_t) * (size_t)(M * L));
   }
-  if (!binA) {
-    HIP_TRY(abuf.alloc(sizeof(int32_t) * (size_t)(M * L), s), "hipMallocAsync (bins)");
-    binA = (int32_t*)abuf.p;
+  if (rerank_k > 0) {
+    l.cv = off;
+    off += align_up(sizeof(float) * (size_t)(M * rerank_k));
+    l.ci = off;
+    off += align_up(sizeof(int32_t) * (size_t)(M * rerank_k));
   }
-  HIP_TRY(launch_prepare(Q, q_dtype, M, db->D, db->metric, dt, false, (unsigned char*)qbuf.p, q_tiles_n, nullptr,
-                         nullptr, s),
-          "query preparation");
-  FusedParams p{};
-  p.db_tiles = db->tiles;
-  p.q_tiles = (const unsigned char*)qbuf.p;
-  p.N = db->N;
-  p.L = L;
-  p.M = M;
-  p.bins_per_chunk = bpc;
-  p.n_chunks = n_chunks;
-  p.n_qb = (int32_t)n_qb;
-  p.out_sign = db->metric == KNN_L2 ? -1.f : 1.f;
-  p.binV = binV;
-  p.binA = binA;
-  p.ldo = L;
-  HIP_TRY(launch_fused(dt, ng, ncb, p, s), "distance + bin-reduce kernel");
-  const unsigned char* qt = (const unsigned char*)qbuf.p;
-  if (bins_idx) HIP_TRY(launch_resolve(dt, binA, M, L, L, qt, db->tiles, ng, s), "resolve bin winners");
-  const bool minimize = db->metric == KNN_L2;
-  if (rerank_k <= 0) {
-    HIP_TRY(launch_select(binV, binA, M, L, L, K, minimize, out_val, out_idx, K, s), "top-K select");
-    HIP_TRY(launch_resolve(dt, out_idx, M, K, K, qt, db->tiles, ng, s), "resolve top-K rows");
-    return KNN_OK;
-  }
-  HIP_TRY(cbufv.alloc(sizeof(float) * (size_t)(M * rerank_k), s), "hipMallocAsync (candidates)");
-  HIP_TRY(cbufi.alloc(sizeof(int32_t) * (size_t)(M * rerank_k), s), "hipMallocAsync (candidates)");
-  HIP_TRY(launch_select(binV, binA, M, L, L, rerank_k, minimize, (float*)cbufv.p, (int32_t*)cbufi.p, rerank_k, s),
-          "top-K select (rerank candidates)");
-  HIP_TRY(launch_resolve(dt, (int32_t*)cbufi.p, M, rerank_k, rerank_k, qt, db->tiles, ng, s),
-          "resolve rerank candidates");
-  HIP_TRY(launch_rerank((const int32_t*)cbufi.p, M, rerank_k, Q, q_dtype, db->X, db->in_dt, db->D, db->metric,
-                        db->orig_half_norm, db->orig_rnorm, K, out_val, out_idx, s),
-          "FP32 rerank");
-  return KNN_OK;
+  l.total = off;
+  return l;
 }
 
-extern "C" knn_status knn_db_search(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, int32_t K,
-                                    int64_t L, int32_t rerank_k, float* out_val, int32_t* out_idx, float* bins_val,
-                                    int32_t* bins_idx, void* stream) {
-  g_last_error.clear();
-  if (!db) return fail(KNN_ERR_INVALID, "db is NULL");
-  if (L <= 0) L = knn_bins_for_recall(K, 0.95, db->N);
+// L of a search: given, or the smallest meeting the recall target (eq. l:approx) for the
+// database's rows or, with an input-size override, for that many rows at the same bin
+// density (the database is then one shard of a longer one).  -1 if invalid.
+int64_t resolve_bins(int64_t N, int32_t K, int64_t L, double recall_target, int64_t input_size_override) {
+  if (L > 0) return L;
+  const double r = recall_target > 0.0 ? recall_target : 0.95;
+  return knn_approx_bins(N, K, r, input_size_override);
+}
+
+knn_status check_search(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, int32_t K, int64_t L,
+                        int32_t rerank_k, const float* out_val, const int32_t* out_idx, const float* bins_val,
+                        const int32_t* bins_idx) {
   knn_status st = check_sizes(M, db->N, db->D, K, L);
   if (st != KNN_OK) return st;
   if (!valid_in(q_dtype)) return fail(KNN_ERR_INVALID, "q_dtype must be KNN_F32 or KNN_BF16");
@@ -391,7 +416,86 @@ extern "C" knn_status knn_db_search(const knn_db* db, const void* Q, int32_t q_d
   if (rerank_k != 0 && (rerank_k < K || rerank_k > L || rerank_k > 1024))
     return fail(KNN_ERR_INVALID, "rerank_k must be 0 or in [K, min(L, 1024)] (got %d)", rerank_k);
   if ((int64_t)M * L >= (int64_t(1) << 40)) return fail(KNN_ERR_UNSUPPORTED, "M * L too large");
-  return search_core(db, Q, q_dtype, M, K, L, rerank_k, out_val, out_idx, bins_val, bins_idx, (hipStream_t)stream);
+  return KNN_OK;
+}
+
+}  // namespace
+
+// every buffer comes from `ws` (search_layout's size, checked by the caller)
+static knn_status search_core(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, int32_t K, int64_t L,
+                              int32_t rerank_k, float* out_val, int32_t* out_idx, float* bins_val,
+                              int32_t* bins_idx, unsigned char* ws, hipStream_t s) {
+  if (M == 0) return KNN_OK;
+  const int dt = db->compute, ng = db->ng;
+  const SearchLayout lay = search_layout(db, M, L, rerank_k, bins_val != nullptr);
+  unsigned char* qbuf = ws + lay.q;
+  float* binV = bins_val ? bins_val : reinterpret_cast<float*>(ws + lay.bv);
+  int32_t* binA = bins_idx ? bins_idx : reinterpret_cast<int32_t*>(ws + lay.ba);
+  HIP_TRY(launch_prepare(Q, q_dtype, M, db->D, db->metric, dt, false, qbuf, lay.q_tiles_n, nullptr, nullptr, s),
+          "query preparation");
+  FusedParams p{};
+  p.db_tiles = db->tiles;
+  p.q_tiles = qbuf;
+  p.N = db->N;
+  p.L = L;
+  p.M = M;
+  p.bins_per_chunk = lay.bpc;
+  p.n_chunks = lay.n_chunks;
+  p.n_qb = (int32_t)lay.n_qb;
+  p.out_sign = db->metric == KNN_L2 ? -1.f : 1.f;
+  p.binV = binV;
+  p.binA = binA;
+  p.ldo = L;
+  HIP_TRY(launch_fused(dt, ng, lay.ncb, p, s), "distance + bin-reduce kernel");
+  if (bins_idx) HIP_TRY(launch_resolve(dt, binA, M, L, L, qbuf, db->tiles, ng, s), "resolve bin winners");
+  const bool minimize = db->metric == KNN_L2;
+  if (rerank_k <= 0) {
+    HIP_TRY(launch_select(binV, binA, M, L, L, K, minimize, out_val, out_idx, K, s), "top-K select");
+    HIP_TRY(launch_resolve(dt, out_idx, M, K, K, qbuf, db->tiles, ng, s), "resolve top-K rows");
+    return KNN_OK;
+  }
+  float* cv = reinterpret_cast<float*>(ws + lay.cv);
+  int32_t* ci = reinterpret_cast<int32_t*>(ws + lay.ci);
+  HIP_TRY(launch_select(binV, binA, M, L, L, rerank_k, minimize, cv, ci, rerank_k, s),
+          "top-K select (rerank candidates)");
+  HIP_TRY(launch_resolve(dt, ci, M, rerank_k, rerank_k, qbuf, db->tiles, ng, s), "resolve rerank candidates");
+  HIP_TRY(launch_rerank(ci, M, rerank_k, Q, q_dtype, db->X, db->in_dt, db->D, db->metric, db->orig_half_norm,
+                        db->orig_rnorm, K, out_val, out_idx, s),
+          "FP32 rerank");
+  return KNN_OK;
+}
+
+extern "C" knn_status knn_db_search_workspace_size(const knn_db* db, int64_t M, int32_t K, int64_t L,
+                                                   double recall_target, int64_t input_size_override,
+                                                   int32_t rerank_k, int32_t with_bins, size_t* bytes) {
+  g_last_error.clear();
+  if (!db || !bytes) return fail(KNN_ERR_INVALID, "db and bytes must be non-NULL");
+  L = resolve_bins(db->N, K, L, recall_target, input_size_override);
+  if (L < 1) return fail(KNN_ERR_INVALID, "cannot derive L (K=%d, recall_target=%g)", K, recall_target);
+  knn_status st = check_sizes(M, db->N, db->D, K, L);
+  if (st != KNN_OK) return st;
+  *bytes = search_layout(db, M, L, rerank_k, with_bins != 0).total;
+  return KNN_OK;
+}
+
+extern "C" knn_status knn_db_search(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, int32_t K,
+                                    int64_t L, double recall_target, int64_t input_size_override, int32_t rerank_k,
+                                    float* out_val, int32_t* out_idx, float* bins_val, int32_t* bins_idx,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!db) return fail(KNN_ERR_INVALID, "db is NULL");
+  L = resolve_bins(db->N, K, L, recall_target, input_size_override);
+  if (L < 1) return fail(KNN_ERR_INVALID, "cannot derive L (K=%d, recall_target=%g)", K, recall_target);
+  knn_status st = check_search(db, Q, q_dtype, M, K, L, rerank_k, out_val, out_idx, bins_val, bins_idx);
+  if (st != KNN_OK) return st;
+  const size_t need = search_layout(db, M, L, rerank_k, bins_val != nullptr).total;
+  if (ws_bytes < need)
+    return fail(KNN_ERR_INVALID, "workspace too small (%zu < %zu bytes, see knn_db_search_workspace_size)",
+                ws_bytes, need);
+  if (need > 0 && (!workspace || reinterpret_cast<uintptr_t>(workspace) % 16 != 0))
+    return fail(KNN_ERR_INVALID, "workspace must be a non-NULL, 16-byte aligned device pointer");
+  return search_core(db, Q, q_dtype, M, K, L, rerank_k, out_val, out_idx, bins_val, bins_idx,
+                     static_cast<unsigned char*>(workspace), (hipStream_t)stream);
 }
 
 extern "C" knn_status knn_search(const float* Q, int64_t M, const float* X, int64_t N, int32_t D, int32_t K,
@@ -415,12 +519,17 @@ extern "C" knn_status knn_search(const float* Q, int64_t M, const float* X, int6
   db.N = N;
   db.n_tiles = ceil_div(N, kTileRows);
   db.X = X;
-  DevBuf tiles;
-  HIP_TRY(tiles.alloc((size_t)(db.n_tiles * tile_bytes(db.ng)), s), "hipMallocAsync (database)");
-  db.tiles = (unsigned char*)tiles.p;
+  // the plain form takes raw rows: it prepares X into a stream-ordered temporary from
+  // the library's pool on every call, followed by the search's own workspace
+  const size_t tiles_bytes = align_up((size_t)(db.n_tiles * tile_bytes(db.ng)));
+  const size_t ws_bytes = search_layout(&db, M, L, 0, false).total;
+  DevBuf tmp;
+  HIP_TRY(tmp.alloc(tiles_bytes + ws_bytes, s), "hipMallocAsync (prepared rows and workspace)");
+  db.tiles = static_cast<unsigned char*>(tmp.p);
   HIP_TRY(launch_prepare(X, KNN_F32, N, D, metric, KNN_F32, true, db.tiles, db.n_tiles, nullptr, nullptr, s),
           "database preparation");
-  return search_core(&db, Q, KNN_F32, M, K, L, 0, out_val, out_idx, nullptr, nullptr, s);
+  return search_core(&db, Q, KNN_F32, M, K, L, 0, out_val, out_idx, nullptr, nullptr,
+                     static_cast<unsigned char*>(tmp.p) + tiles_bytes, s);
 }
 
 // --------------------------------------------------------------------------- separate steps
@@ -521,11 +630,14 @@ extern "C" int64_t knn_approx_bins(int64_t n, int32_t K, double recall_target, i
   return std::min<int64_t>(std::max<int64_t>(L, K), n);
 }
 
-extern "C" knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_t rows, int64_t cols, int64_t ld,
-                                       int32_t reduction_dim, int32_t K, double recall_target,
-                                       int64_t input_size_override, int64_t L, int32_t minimize,
-                                       int32_t aggregate_to_topk, float* out_val, int32_t* out_idx, void* stream) {
-  g_last_error.clear();
+namespace {
+
+// Checks the op's arguments and resolves L; on success B (slices), n (slice length)
+// and L are set and the workspace need (bins of every slice when aggregating) is returned
+// in *ws.
+knn_status approx_args(int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int32_t& reduction_dim, int32_t K,
+                       double recall_target, int64_t input_size_override, int64_t& L, int32_t minimize,
+                       int32_t aggregate_to_topk, int64_t& B, int64_t& n, size_t* ws) {
   if (dtype != KNN_F32 && dtype != KNN_BF16) return fail(KNN_ERR_INVALID, "dtype must be KNN_F32 or KNN_BF16");
   if (rows < 0 || cols < 0) return fail(KNN_ERR_INVALID, "rows and cols must be >= 0");
   if (ld < cols || ld < 1) return fail(KNN_ERR_INVALID, "need ld >= max(cols, 1) (ld=%lld)", (long long)ld);
@@ -533,7 +645,8 @@ extern "C" knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_
   if (reduction_dim != 0 && reduction_dim != 1) return fail(KNN_ERR_INVALID, "reduction_dim must be 0, 1 or -1");
   if (minimize != 0 && minimize != 1) return fail(KNN_ERR_INVALID, "minimize must be 0 or 1");
   if (aggregate_to_topk != 0 && aggregate_to_topk != 1) return fail(KNN_ERR_INVALID, "aggregate_to_topk must be 0 or 1");
-  const int64_t n = reduction_dim == 1 ? cols : rows, B = reduction_dim == 1 ? rows : cols;
+  n = reduction_dim == 1 ? cols : rows;
+  B = reduction_dim == 1 ? rows : cols;
   if (n < 1 || n > kMaxRows)
     return fail(KNN_ERR_INVALID, "the reduced dimension must have 1 .. 2^31 - 64 entries (got %lld)", (long long)n);
   if (K < 1 || K > n) return fail(KNN_ERR_INVALID, "need 1 <= K <= reduced size (K=%d, n=%lld)", K, (long long)n);
@@ -545,9 +658,43 @@ extern "C" knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_
   }
   if (L < K || L > n)
     return fail(KNN_ERR_INVALID, "need K <= L <= reduced size (K=%d, L=%lld, n=%lld)", K, (long long)L, (long long)n);
+  *ws = (aggregate_to_topk && B > 0) ? align_up(sizeof(float) * (size_t)(B * L)) + align_up(sizeof(int32_t) * (size_t)(B * L))
+                                     : 0;
+  return KNN_OK;
+}
+
+}  // namespace
+
+extern "C" knn_status knn_approx_workspace_size(int32_t dtype, int64_t rows, int64_t cols, int64_t ld,
+                                                int32_t reduction_dim, int32_t K, double recall_target,
+                                                int64_t input_size_override, int64_t L, int32_t minimize,
+                                                int32_t aggregate_to_topk, size_t* bytes) {
+  g_last_error.clear();
+  if (!bytes) return fail(KNN_ERR_INVALID, "bytes is NULL");
+  int64_t B = 0, n = 0;
+  return approx_args(dtype, rows, cols, ld, reduction_dim, K, recall_target, input_size_override, L, minimize,
+                     aggregate_to_topk, B, n, bytes);
+}
+
+extern "C" knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_t rows, int64_t cols, int64_t ld,
+                                       int32_t reduction_dim, int32_t K, double recall_target,
+                                       int64_t input_size_override, int64_t L, int32_t minimize,
+                                       int32_t aggregate_to_topk, float* out_val, int32_t* out_idx, void* workspace,
+                                       size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  int64_t B = 0, n = 0;
+  size_t need = 0;
+  knn_status st = approx_args(dtype, rows, cols, ld, reduction_dim, K, recall_target, input_size_override, L,
+                              minimize, aggregate_to_topk, B, n, &need);
+  if (st != KNN_OK) return st;
   if (B > 0 && (!scores || !out_val || !out_idx)) return fail(KNN_ERR_INVALID, "scores and outputs must be non-NULL");
   const size_t esz = dtype == KNN_F32 ? 4 : 2;
   if (reinterpret_cast<uintptr_t>(scores) % esz != 0) return fail(KNN_ERR_INVALID, "scores must be %zu-byte aligned", esz);
+  if (ws_bytes < need)
+    return fail(KNN_ERR_INVALID, "workspace too small (%zu < %zu bytes, see knn_approx_workspace_size)", ws_bytes,
+                need);
+  if (need > 0 && (!workspace || reinterpret_cast<uintptr_t>(workspace) % 16 != 0))
+    return fail(KNN_ERR_INVALID, "workspace must be a non-NULL, 16-byte aligned device pointer");
   if (B == 0) return KNN_OK;
   hipStream_t s = (hipStream_t)stream;
   const int dt = dtype == KNN_F32 ? DT_F32 : DT_BF16;
@@ -556,11 +703,8 @@ extern "C" knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_
             "approx bins");
     return KNN_OK;
   }
-  DevBuf vbuf, abuf;
-  HIP_TRY(vbuf.alloc(sizeof(float) * (size_t)(B * L), s), "hipMallocAsync (bins)");
-  HIP_TRY(abuf.alloc(sizeof(int32_t) * (size_t)(B * L), s), "hipMallocAsync (bins)");
-  float* V = static_cast<float*>(vbuf.p);
-  int32_t* A = static_cast<int32_t*>(abuf.p);
+  float* V = static_cast<float*>(workspace);
+  int32_t* A = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(workspace) + align_up(sizeof(float) * (size_t)(B * L)));
   HIP_TRY(launch_approx_bins(scores, dt, rows, cols, ld, reduction_dim, L, minimize != 0, V, A, s), "approx bins");
   if (reduction_dim == 1)  // bins B x L, results B x K
     HIP_TRY(launch_select(V, A, B, L, L, K, minimize != 0, out_val, out_idx, K, s), "top-K");
@@ -572,48 +716,171 @@ extern "C" knn_status knn_approx_top_k(const void* scores, int32_t dtype, int64_
 // --------------------------------------------------------------------------- batched plan
 namespace {
 
-void free_plan_buffers(knn_plan* p) {
-  for (auto& g : p->groups) {
-    if (g.q_tiles) (void)hipFree(g.q_tiles);
-    if (g.binV) (void)hipFree(g.binV);
-    if (g.binA) (void)hipFree(g.binA);
-    g.q_tiles = nullptr;
-    g.binV = nullptr;
-    g.binA = nullptr;
-  }
-  if (p->d_segs) (void)hipFree(p->d_segs);
-  if (p->d_groups) (void)hipFree(p->d_groups);
-  if (p->d_items) (void)hipFree(p->d_items);
-  if (p->d_sel) (void)hipFree(p->d_sel);
-  p->d_segs = nullptr;
-  p->d_groups = nullptr;
-  p->d_items = nullptr;
-  p->d_sel = nullptr;
+constexpr int kPlanBlocksPerXcd = 64;  // 2 resident workgroups on each of an XCD's 32 CUs
+constexpr int kPlanBlocks = 8 * kPlanBlocksPerXcd;
+
+void set_group_shape(GroupPlan& g) {
+  const int64_t QB = (int64_t)kWaves * 32 * g.ncb;
+  g.n_qb = ceil_div(std::max<int64_t>(g.M, 1), QB);
+  g.q_tiles_n = g.n_qb * QB / kTileRows;
+  g.n_chunks = ceil_div(g.L, g.bins_per_chunk);
 }
 
-// build (or rebuild after tuning) every device buffer and descriptor of the plan
-knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
-  free_plan_buffers(p);
-  const int dt = p->compute;
-  std::vector<QSeg> segs;
-  std::vector<GroupDesc> gds;
-  std::vector<SelRow> sel;
+// the autotuner's candidates for one group: L at or above the L2-resident choice (a bin
+// that does not fit the 2 MiB an XCD's workgroups stream through its L2 is re-fetched
+// by every query block), ncb in {1, 2}, two work-item sizes
+std::vector<GroupPlan> tune_candidates(const knn_plan* p, const GroupPlan& g) {
+  std::vector<GroupPlan> out;
+  const knn_db* db = p->dbs[g.db];
+  const int64_t N = db->N;
+  const int64_t Lfit = std::min<int64_t>(N, std::max(g.L_min, bins_for_l2(N, db->ng)));
+  for (int64_t Lc : {Lfit, std::min<int64_t>(N, 2 * Lfit)}) {
+    for (int ncb : {1, 2}) {
+      if (!fused_supported(p->compute, db->ng, ncb)) continue;
+      const int64_t QB = (int64_t)kWaves * 32 * ncb;
+      const int64_t nqb = ceil_div(std::max<int64_t>(g.M, 1), QB);
+      for (int64_t target : {int64_t(1024), int64_t(4096)}) {
+        GroupPlan c = g;
+        c.L = Lc;
+        c.ncb = ncb;
+        c.bins_per_chunk = pick_bins_per_chunk(N, Lc, nqb, db->ng, target);
+        set_group_shape(c);
+        bool dup = false;
+        for (const auto& o : out) dup |= (o.L == c.L && o.ncb == c.ncb && o.bins_per_chunk == c.bins_per_chunk);
+        if (!dup) out.push_back(c);
+      }
+    }
+  }
+  return out;
+}
+
+// Device memory of the plan for its current choices, as offsets into the workspace:
+// per group the prepared queries and the M x L bins, then the descriptors, then the
+// autotuner's top-K output.  With `items_bound` >= 0 the work list is sized for that
+// many items instead of the current ones.
+struct PlanLayout {
+  std::vector<size_t> q, bv, ba;
+  size_t segs = 0, gds = 0, items = 0, sel = 0, tv = 0, ti = 0, total = 0;
+};
+
+int64_t count_sel_rows(const knn_plan* p) {
+  int64_t n = 0;
+  for (const auto& b : p->batches) n += b.M;
+  return n;
+}
+
+PlanLayout plan_layout(const knn_plan* p, const std::vector<GroupPlan>& groups, int64_t n_items) {
+  PlanLayout l;
+  size_t off = 0;
+  int64_t tune_rows = 0;
+  for (const auto& g : groups) {
+    const knn_db* db = p->dbs[g.db];
+    l.q.push_back(off);
+    off += align_up((size_t)(g.q_tiles_n * tile_bytes(db->ng)));
+    l.bv.push_back(off);
+    off += align_up(sizeof(float) * (size_t)std::max<int64_t>(1, g.M * g.L));
+    l.ba.push_back(off);
+    off += align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(1, g.M * g.L));
+    tune_rows = std::max<int64_t>(tune_rows, g.M * g.K_max);
+  }
+  l.segs = off;
+  off += align_up(sizeof(QSeg) * (p->batches.size() + groups.size() + 1));
+  l.gds = off;
+  off += align_up(sizeof(GroupDesc) * (groups.size() + 1));
+  l.items = off;
+  off += align_up(sizeof(WorkItem) * (size_t)std::max<int64_t>(1, n_items));
+  l.sel = off;
+  off += align_up(sizeof(SelRow) * (size_t)std::max<int64_t>(1, count_sel_rows(p)));
+  l.tv = off;
+  off += align_up(sizeof(float) * (size_t)std::max<int64_t>(1, tune_rows));
+  l.ti = off;
+  off += align_up(sizeof(int32_t) * (size_t)std::max<int64_t>(1, tune_rows));
+  l.total = off;
+  return l;
+}
+
+// work list: chunks dealt round-robin to the 8 XCDs; the items of one chunk (all its
+// query blocks) are consecutive in that XCD's list, so the persistent workgroups of one
+// XCD share a chunk's tiles through its L2.  Padded to whole rounds of kPlanBlocks.
+std::vector<WorkItem> build_items(const std::vector<GroupPlan>& groups) {
+  std::vector<std::vector<WorkItem>> per_xcd(8);
+  int64_t chunk_seq = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const GroupPlan& g = groups[gi];
+    if (g.M == 0) continue;
+    for (int64_t c = 0; c < g.n_chunks; ++c, ++chunk_seq) {
+      auto& lst = per_xcd[chunk_seq % 8];
+      for (int64_t qb = 0; qb < g.n_qb; ++qb) {
+        WorkItem it{};
+        it.grp = (int32_t)gi;
+        it.qb = (int32_t)qb;
+        it.b0 = c * g.bins_per_chunk;
+        it.b1 = std::min(g.L, it.b0 + g.bins_per_chunk);
+        lst.push_back(it);
+      }
+    }
+  }
+  size_t rounds = 0;
+  for (auto& l : per_xcd) rounds = std::max<size_t>(rounds, (size_t)ceil_div((int64_t)l.size(), kPlanBlocksPerXcd));
+  std::vector<WorkItem> items(rounds * kPlanBlocks);
+  for (size_t r = 0; r < rounds; ++r)
+    for (int w = 0; w < kPlanBlocks; ++w) {
+      const int x = w % 8, i = w / 8;
+      const size_t k = r * kPlanBlocksPerXcd + i;
+      WorkItem it{};
+      it.grp = -1;
+      if (k < per_xcd[x].size()) it = per_xcd[x][k];
+      items[r * kPlanBlocks + w] = it;
+    }
+  return items;
+}
+
+// Upper bound of the work list over every choice the autotuner may try: per XCD at most
+// ceil(chunks / 8) + 1 chunks of each group, each with its query blocks.
+int64_t items_bound(const knn_plan* p) {
+  int64_t per_xcd = 0;
+  for (const auto& g : p->groups) {
+    if (g.M == 0) continue;
+    int64_t worst = (ceil_div(g.n_chunks, 8) + 1) * g.n_qb;
+    if (g.tune)
+      for (const auto& c : tune_candidates(p, g)) worst = std::max(worst, (ceil_div(c.n_chunks, 8) + 1) * c.n_qb);
+    per_xcd += worst;
+  }
+  return ceil_div(std::max<int64_t>(per_xcd, 1), kPlanBlocksPerXcd) * kPlanBlocks;
+}
+
+size_t plan_bound_bytes(const knn_plan* p) {
+  // every group at its largest candidate buffers, the work list at its bound
+  std::vector<GroupPlan> big = p->groups;
+  for (auto& g : big) {
+    if (!g.tune) continue;
+    for (const auto& c : tune_candidates(p, g)) {
+      if (c.M * c.L > g.M * g.L) g.L = c.L;
+      if (c.q_tiles_n > g.q_tiles_n) g.q_tiles_n = c.q_tiles_n;
+    }
+  }
+  return plan_layout(p, big, items_bound(p)).total;
+}
+
+// Lay out the plan's current choices in the workspace and upload its descriptors.
+knn_status bind_plan(knn_plan* p, unsigned char* ws, hipStream_t s) {
+  for (auto& g : p->groups) set_group_shape(g);
+  p->items = build_items(p->groups);
+  const PlanLayout lay = plan_layout(p, p->groups, items_bound(p));
+  p->segs.clear();
+  p->gds.clear();
+  p->sel.clear();
   int64_t first = 0;
   p->max_ng = 0;
   p->lds_bytes = 0;
   for (size_t gi = 0; gi < p->groups.size(); ++gi) {
     GroupPlan& g = p->groups[gi];
     const knn_db* db = p->dbs[g.db];
-    const int64_t QB = (int64_t)kWaves * 32 * g.ncb;
-    g.n_qb = ceil_div(std::max<int64_t>(g.M, 1), QB);
-    g.q_tiles_n = g.n_qb * QB / kTileRows;
-    g.n_chunks = ceil_div(g.L, g.bins_per_chunk);
+    g.q_tiles = ws + lay.q[gi];
+    g.binV = reinterpret_cast<float*>(ws + lay.bv[gi]);
+    g.binA = reinterpret_cast<int32_t*>(ws + lay.ba[gi]);
     p->max_ng = std::max(p->max_ng, db->ng);
     p->lds_bytes = std::max(p->lds_bytes, fused_lds_bytes(p->compute, db->ng, g.ncb));
-    if (hipMalloc(&g.q_tiles, (size_t)(g.q_tiles_n * tile_bytes(db->ng))) != hipSuccess ||
-        hipMalloc(&g.binV, sizeof(float) * (size_t)std::max<int64_t>(1, g.M * g.L)) != hipSuccess ||
-        hipMalloc(&g.binA, sizeof(int32_t) * (size_t)std::max<int64_t>(1, g.M * g.L)) != hipSuccess)
-      return fail(KNN_ERR_OOM, "hipMalloc for the batched plan");
     // query segments: the batches of this group in order, then padding rows
     int64_t row = 0;
     for (const auto& b : p->batches) {
@@ -627,7 +894,7 @@ knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
       q.ng = db->ng;
       q.metric = db->metric;
       q.tiles = g.q_tiles;
-      segs.push_back(q);
+      p->segs.push_back(q);
       for (int64_t r = 0; r < b.M; ++r) {
         SelRow sr{};
         sr.V = g.binV + (row + r) * g.L;
@@ -641,7 +908,7 @@ knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
         sr.db_tiles = db->tiles;
         sr.q_row = row + r;
         sr.ng = db->ng;
-        sel.push_back(sr);
+        p->sel.push_back(sr);
       }
       first += b.M;
       row += b.M;
@@ -657,7 +924,7 @@ knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
       q.ng = db->ng;
       q.metric = db->metric;
       q.tiles = g.q_tiles;
-      segs.push_back(q);
+      p->segs.push_back(q);
       first += padded - row;
     }
     GroupDesc gd{};
@@ -672,57 +939,29 @@ knn_status build_plan_buffers(knn_plan* p, hipStream_t s) {
     gd.ldo = g.L;
     gd.ng = db->ng;
     gd.ncb = g.ncb;
-    gds.push_back(gd);
+    p->gds.push_back(gd);
   }
   p->total_q_rows = first;
-  p->n_segs = (int)segs.size();
-  p->n_sel_rows = (int64_t)sel.size();
-  // work list: chunks dealt round-robin to the 8 XCDs; the items of one chunk
-  // (all its query blocks) are consecutive in that XCD's list, so the persistent
-  // workgroups of one XCD share a chunk's tiles through its L2
-  std::vector<std::vector<WorkItem>> per_xcd(8);
-  int64_t chunk_seq = 0;
-  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
-    const GroupPlan& g = p->groups[gi];
-    if (g.M == 0) continue;
-    for (int64_t c = 0; c < g.n_chunks; ++c, ++chunk_seq) {
-      auto& lst = per_xcd[chunk_seq % 8];
-      for (int64_t qb = 0; qb < g.n_qb; ++qb) {
-        WorkItem it{};
-        it.grp = (int32_t)gi;
-        it.qb = (int32_t)qb;
-        it.b0 = c * g.bins_per_chunk;
-        it.b1 = std::min(g.L, it.b0 + g.bins_per_chunk);
-        lst.push_back(it);
-      }
-    }
-  }
-  const int blocks_per_xcd = 64;  // 2 resident workgroups on each of an XCD's 32 CUs
-  p->n_blocks = 8 * blocks_per_xcd;
-  size_t rounds = 0;
-  for (auto& l : per_xcd) rounds = std::max<size_t>(rounds, (size_t)ceil_div((int64_t)l.size(), blocks_per_xcd));
-  std::vector<WorkItem> items(rounds * p->n_blocks);
-  for (size_t r = 0; r < rounds; ++r)
-    for (int w = 0; w < p->n_blocks; ++w) {
-      const int x = w % 8, i = w / 8;
-      const size_t k = r * blocks_per_xcd + i;
-      WorkItem it{};
-      it.grp = -1;
-      if (k < per_xcd[x].size()) it = per_xcd[x][k];
-      items[r * p->n_blocks + w] = it;
-    }
-  p->n_items = (int64_t)items.size();
-  if (hipMalloc(&p->d_segs, sizeof(QSeg) * std::max<size_t>(1, segs.size())) != hipSuccess ||
-      hipMalloc(&p->d_groups, sizeof(GroupDesc) * std::max<size_t>(1, gds.size())) != hipSuccess ||
-      hipMalloc(&p->d_items, sizeof(WorkItem) * std::max<size_t>(1, items.size())) != hipSuccess ||
-      hipMalloc(&p->d_sel, sizeof(SelRow) * std::max<size_t>(1, sel.size())) != hipSuccess)
-    return fail(KNN_ERR_OOM, "hipMalloc for the batched plan descriptors");
-  HIP_TRY(hipMemcpyAsync(p->d_segs, segs.data(), sizeof(QSeg) * segs.size(), hipMemcpyHostToDevice, s), "upload");
-  HIP_TRY(hipMemcpyAsync(p->d_groups, gds.data(), sizeof(GroupDesc) * gds.size(), hipMemcpyHostToDevice, s),
+  p->n_segs = (int)p->segs.size();
+  p->n_sel_rows = (int64_t)p->sel.size();
+  p->n_blocks = kPlanBlocks;
+  p->n_items = (int64_t)p->items.size();
+  p->d_segs = reinterpret_cast<QSeg*>(ws + lay.segs);
+  p->d_groups = reinterpret_cast<GroupDesc*>(ws + lay.gds);
+  p->d_items = reinterpret_cast<WorkItem*>(ws + lay.items);
+  p->d_sel = reinterpret_cast<SelRow*>(ws + lay.sel);
+  p->tune_val = reinterpret_cast<float*>(ws + lay.tv);
+  p->tune_idx = reinterpret_cast<int32_t*>(ws + lay.ti);
+  HIP_TRY(hipMemcpyAsync(p->d_segs, p->segs.data(), sizeof(QSeg) * p->segs.size(), hipMemcpyHostToDevice, s),
           "upload");
-  HIP_TRY(hipMemcpyAsync(p->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, s),
+  HIP_TRY(hipMemcpyAsync(p->d_groups, p->gds.data(), sizeof(GroupDesc) * p->gds.size(), hipMemcpyHostToDevice, s),
           "upload");
-  HIP_TRY(hipMemcpyAsync(p->d_sel, sel.data(), sizeof(SelRow) * sel.size(), hipMemcpyHostToDevice, s), "upload");
+  HIP_TRY(hipMemcpyAsync(p->d_items, p->items.data(), sizeof(WorkItem) * p->items.size(), hipMemcpyHostToDevice, s),
+          "upload");
+  if (!p->sel.empty())
+    HIP_TRY(hipMemcpyAsync(p->d_sel, p->sel.data(), sizeof(SelRow) * p->sel.size(), hipMemcpyHostToDevice, s),
+            "upload");
+  // the host descriptors are rewritten by the next bind: wait for the copies
   HIP_TRY(hipStreamSynchronize(s), "sync");
   return KNN_OK;
 }
@@ -737,7 +976,8 @@ knn_status run_plan(knn_plan* p, hipStream_t s) {
   return KNN_OK;
 }
 
-// time one group alone with a given (ncb, L, bins_per_chunk), non-persistent launch
+// time one group alone with its current (ncb, L, bins_per_chunk): non-persistent
+// distance launch + top-K, best of 3, the queries prepared by the plan's own launch
 double time_group(knn_plan* p, size_t gi, hipStream_t s) {
   const GroupPlan& g = p->groups[gi];
   const knn_db* db = p->dbs[g.db];
@@ -754,34 +994,29 @@ double time_group(knn_plan* p, size_t gi, hipStream_t s) {
   fp.binV = g.binV;
   fp.binA = g.binA;
   fp.ldo = g.L;
-  float* ov = nullptr;
-  int32_t* oi = nullptr;
-  if (hipMalloc(&ov, sizeof(float) * (size_t)(g.M * g.K_max)) != hipSuccess) return 1e30;
-  if (hipMalloc(&oi, sizeof(int32_t) * (size_t)(g.M * g.K_max)) != hipSuccess) {
-    (void)hipFree(ov);
-    return 1e30;
-  }
   hipEvent_t a, b;
   double best = 1e30;
-  if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
-      launch_prepare_segments(p->d_segs, p->n_segs, p->total_q_rows, p->q_dtype, p->compute, s) == hipSuccess &&
+  if (hipEventCreate(&a) != hipSuccess) return best;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return best;
+  }
+  if (launch_prepare_segments(p->d_segs, p->n_segs, p->total_q_rows, p->q_dtype, p->compute, s) == hipSuccess &&
       launch_fused(db->compute, db->ng, g.ncb, fp, s) == hipSuccess) {  // warm-up
     for (int rep = 0; rep < 3; ++rep) {
       (void)hipEventRecord(a, s);
       (void)launch_fused(db->compute, db->ng, g.ncb, fp, s);
-      (void)launch_select(g.binV, g.binA, g.M, g.L, g.L, g.K_max, false, ov, oi, g.K_max, s);
+      (void)launch_select(g.binV, g.binA, g.M, g.L, g.L, g.K_max, false, p->tune_val, p->tune_idx, g.K_max, s);
       (void)hipEventRecord(b, s);
       (void)hipEventSynchronize(b);
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, a, b);
       best = std::min(best, (double)ms);
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
   }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   (void)hipStreamSynchronize(s);
-  (void)hipFree(ov);
-  (void)hipFree(oi);
   return best;
 }
 
@@ -793,14 +1028,14 @@ std::string tune_key(const knn_plan* p, const GroupPlan& g) {
   (void)hipGetDeviceProperties(&prop, dev);
   std::ostringstream o;
   o << prop.gcnArchName << "|dt" << db->compute << "|m" << db->metric << "|N" << db->N << "|D" << db->D << "|M"
-    << g.M << "|K" << g.K_max;
+    << g.M << "|K" << g.K_max << "|Lmin" << g.L_min;
   return o.str();
 }
 
 // tiny JSON cache: {"key": [L, ncb, bins_per_chunk], ...}
-std::map<std::string, std::vector<int64_t>> read_cache(const char* path) {
+std::map<std::string, std::vector<int64_t>> read_cache(const std::string& path) {
   std::map<std::string, std::vector<int64_t>> m;
-  if (!path) return m;
+  if (path.empty()) return m;
   std::ifstream f(path);
   if (!f) return m;
   std::string all((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
@@ -822,8 +1057,8 @@ std::map<std::string, std::vector<int64_t>> read_cache(const char* path) {
   return m;
 }
 
-void write_cache(const char* path, const std::map<std::string, std::vector<int64_t>>& m) {
-  if (!path) return;
+void write_cache(const std::string& path, const std::map<std::string, std::vector<int64_t>>& m) {
+  if (path.empty()) return;
   std::ofstream f(path);
   if (!f) return;
   f << "{\n";
@@ -836,13 +1071,26 @@ void write_cache(const char* path, const std::map<std::string, std::vector<int64
   f << "}\n";
 }
 
+// A cached choice is used only if it is one the plan could have made: L between the
+// recall bound (and K) and N, a kernel instance that exists, whole bins per item.
+bool cached_choice_valid(const knn_plan* p, const GroupPlan& g, const std::vector<int64_t>& v) {
+  if (v.size() != 3) return false;
+  const knn_db* db = p->dbs[g.db];
+  const int64_t L = v[0], ncb = v[1], bpc = v[2];
+  if (L < std::max<int64_t>(g.L_min, g.K_max) || L > db->N) return false;
+  if (ncb != 1 && ncb != 2) return false;
+  if (!fused_supported(p->compute, db->ng, (int)ncb)) return false;
+  return bpc >= 1 && bpc <= L;
+}
+
 }  // namespace
 
 extern "C" knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn_batch* batches, int32_t nb,
                                       int32_t q_dtype, double recall_target, int32_t tune, const char* cache_path,
-                                      void* stream, knn_plan** out) {
+                                      knn_plan** out) {
   g_last_error.clear();
   if (!out) return fail(KNN_ERR_INVALID, "out is NULL");
+  *out = nullptr;
   if (!dbs || ndb < 1) return fail(KNN_ERR_INVALID, "need at least one database");
   if (!batches || nb < 1) return fail(KNN_ERR_INVALID, "need at least one batch");
   if (!valid_in(q_dtype)) return fail(KNN_ERR_INVALID, "q_dtype must be KNN_F32 or KNN_BF16");
@@ -864,13 +1112,13 @@ extern "C" knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn
     if (x.K < 1 || x.K > 1024 || x.K > dbs[x.db]->N) return fail(KNN_ERR_INVALID, "batch %d: bad K %d", b, x.K);
     if (x.M > 0 && (!x.Q || !x.out_val || !x.out_idx)) return fail(KNN_ERR_INVALID, "batch %d: NULL pointer", b);
   }
-  hipStream_t s = (hipStream_t)stream;
   auto* p = new (std::nothrow) knn_plan();
   if (!p) return fail(KNN_ERR_OOM, "host allocation");
   p->dbs.assign(dbs, dbs + ndb);
   p->batches.assign(batches, batches + nb);
   p->q_dtype = q_dtype;
   p->compute = compute;
+  if (cache_path) p->cache_path = cache_path;
   for (int d = 0; d < ndb; ++d) {
     GroupPlan g;
     g.db = d;
@@ -887,74 +1135,78 @@ extern "C" knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn
     g.ncb = g.M > 128 ? 2 : 1;
     const int64_t QB = (int64_t)kWaves * 32 * g.ncb;
     g.bins_per_chunk = pick_bins_per_chunk(N, g.L, ceil_div(std::max<int64_t>(g.M, 1), QB), dbs[d]->ng, 4096);
+    set_group_shape(g);
     p->groups.push_back(g);
   }
-  knn_status st = build_plan_buffers(p, s);
-  if (st != KNN_OK) {
-    knn_plan_destroy(p);
-    return st;
-  }
   if (tune) {
-    auto cache = read_cache(cache_path);
-    bool dirty = false;
-    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
-      GroupPlan& g = p->groups[gi];
+    const auto cache = read_cache(p->cache_path);
+    for (auto& g : p->groups) {
       if (g.M == 0) continue;
-      const std::string key = tune_key(p, g);
-      auto it = cache.find(key);
-      if (it != cache.end() && it->second.size() == 3) {
+      auto it = cache.find(tune_key(p, g));
+      if (it != cache.end() && cached_choice_valid(p, g, it->second)) {
         g.L = it->second[0];
         g.ncb = (int32_t)it->second[1];
         g.bins_per_chunk = it->second[2];
-        continue;
+        set_group_shape(g);
+      } else {
+        g.tune = true;  // timed in knn_plan_setup
       }
-      // candidates: L in {L_min, 2 L_min, 4 L_min, the L2-resident choice} (never
-      // below the recall bound), ncb in {1, 2}, work-item sizes around the heuristic
-      const int64_t N = dbs[g.db]->N;
-      const int64_t Lmin = g.L_min;
-      double best = 1e30;
-      GroupPlan bestg = g;
-      const int64_t Lfit = std::max(Lmin, bins_for_l2(N, dbs[g.db]->ng));
-      for (int64_t Lc0 : {Lmin, 2 * Lmin, 4 * Lmin, Lfit}) {
-        const int64_t Lc = std::min<int64_t>(N, Lc0);
-        for (int ncb : {1, 2}) {
-          if (!fused_supported(compute, dbs[g.db]->ng, ncb)) continue;
-          const int64_t QB = (int64_t)kWaves * 32 * ncb;
-          const int64_t nqb = ceil_div(g.M, QB);
-          for (int64_t target : {int64_t(1024), int64_t(4096)}) {
-            GroupPlan c = g;
-            c.L = Lc;
-            c.ncb = ncb;
-            c.bins_per_chunk = pick_bins_per_chunk(N, Lc, nqb, dbs[g.db]->ng, target);
-            p->groups[gi] = c;
-            if (build_plan_buffers(p, s) != KNN_OK) continue;
-            double ms = time_group(p, gi, s);
-            if (ms < best) {
-              best = ms;
-              bestg = p->groups[gi];
-            }
-          }
-        }
-      }
-      g = bestg;
-      p->groups[gi] = bestg;
-      cache[key] = {g.L, g.ncb, g.bins_per_chunk};
-      dirty = true;
-    }
-    if (dirty) write_cache(cache_path, cache);
-    st = build_plan_buffers(p, s);
-    if (st != KNN_OK) {
-      knn_plan_destroy(p);
-      return st;
     }
   }
   *out = p;
   return KNN_OK;
 }
 
+extern "C" knn_status knn_plan_workspace_size(const knn_plan* plan, size_t* bytes) {
+  g_last_error.clear();
+  if (!plan || !bytes) return fail(KNN_ERR_INVALID, "plan and bytes must be non-NULL");
+  *bytes = plan_bound_bytes(plan);
+  return KNN_OK;
+}
+
+extern "C" knn_status knn_plan_setup(knn_plan* p, void* workspace, size_t ws_bytes, void* stream) {
+  g_last_error.clear();
+  if (!p) return fail(KNN_ERR_INVALID, "plan is NULL");
+  const size_t need = plan_bound_bytes(p);
+  if (ws_bytes < need)
+    return fail(KNN_ERR_INVALID, "workspace too small (%zu < %zu bytes, see knn_plan_workspace_size)", ws_bytes, need);
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 16 != 0)
+    return fail(KNN_ERR_INVALID, "workspace must be a non-NULL, 16-byte aligned device pointer");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  p->bound = false;
+  bool tuned = false;
+  auto cache = read_cache(p->cache_path);
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    if (!p->groups[gi].tune) continue;
+    const GroupPlan start = p->groups[gi];
+    double best = 1e30;
+    GroupPlan bestg = start;
+    for (const auto& c : tune_candidates(p, start)) {
+      p->groups[gi] = c;
+      if (bind_plan(p, ws, s) != KNN_OK) continue;
+      const double ms = time_group(p, gi, s);
+      if (ms < best) {
+        best = ms;
+        bestg = c;
+      }
+    }
+    bestg.tune = false;
+    p->groups[gi] = bestg;
+    cache[tune_key(p, bestg)] = {bestg.L, bestg.ncb, bestg.bins_per_chunk};
+    tuned = true;
+  }
+  if (tuned) write_cache(p->cache_path, cache);
+  knn_status st = bind_plan(p, ws, s);
+  if (st != KNN_OK) return st;
+  p->bound = true;
+  return KNN_OK;
+}
+
 extern "C" knn_status knn_search_batched(knn_plan* plan, void* stream) {
   g_last_error.clear();
   if (!plan) return fail(KNN_ERR_INVALID, "plan is NULL");
+  if (!plan->bound) return fail(KNN_ERR_INVALID, "plan has no workspace: call knn_plan_setup first");
   return run_plan(plan, (hipStream_t)stream);
 }
 
@@ -971,8 +1223,6 @@ extern "C" knn_status knn_plan_info(const knn_plan* plan, int64_t* L, int32_t* q
 }
 
 extern "C" knn_status knn_plan_destroy(knn_plan* plan) {
-  if (!plan) return KNN_OK;
-  free_plan_buffers(plan);
-  delete plan;
+  delete plan;  // its workspace is the caller's memory
   return KNN_OK;
 }

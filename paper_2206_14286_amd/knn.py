@@ -42,6 +42,7 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_14286_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        SZ = ctypes.c_size_t
         sig = {
             "knn_bins_for_recall": (i64, [i32, f64, i64]),
             "knn_expected_recall_bound": (f64, [i32, i64]),
@@ -49,23 +50,29 @@ def lib():
             "knn_status_string": (ctypes.c_char_p, [i32]),
             "knn_last_error": (ctypes.c_char_p, []),
             "knn_device_count": (i32, []),
-            "knn_db_create": (i32, [P, i32, i64, i32, i32, i32, P, ctypes.POINTER(P)]),
+            "knn_db_prepare_size": (SZ, [i64, i32, i32, i32]),
+            "knn_db_prepare": (i32, [P, i32, i64, i32, i32, i32, P, SZ, P, ctypes.POINTER(P)]),
             "knn_db_destroy": (i32, [P]),
             "knn_db_export": (i32, [P, P, P, P, P]),
             "knn_search": (i32, [P, i64, P, i64, i32, i32, i64, i32, P, P, P]),
-            "knn_db_search": (i32, [P, P, i32, i64, i32, i64, i32, P, P, P, P, P]),
+            "knn_db_search": (i32, [P, P, i32, i64, i32, i64, f64, i64, i32, P, P, P, P, P, SZ, P]),
+            "knn_db_search_workspace_size": (i32, [P, i64, i32, i64, f64, i64, i32, i32, ctypes.POINTER(SZ)]),
             "knn_plan_create": (i32, [ctypes.POINTER(P), i32, ctypes.POINTER(KnnBatch), i32, i32, f64, i32,
-                                      ctypes.c_char_p, P, ctypes.POINTER(P)]),
+                                      ctypes.c_char_p, ctypes.POINTER(P)]),
+            "knn_plan_workspace_size": (i32, [P, ctypes.POINTER(SZ)]),
+            "knn_plan_setup": (i32, [P, P, SZ, P]),
             "knn_search_batched": (i32, [P, P]),
             "knn_plan_info": (i32, [P, P, P, P]),
             "knn_plan_destroy": (i32, [P]),
             "knn_backward": (i32, [P, P, P, P, i32, i64, i64, i32, i32, i32, P, P, P]),
-            "knn_query_buffer_bytes": (ctypes.c_size_t, [P, i64]),
-            "knn_query_prepare": (i32, [P, P, i32, i64, P, ctypes.c_size_t, P]),
+            "knn_query_buffer_bytes": (SZ, [P, i64]),
+            "knn_query_prepare": (i32, [P, P, i32, i64, P, SZ, P]),
             "knn_partial_reduce": (i32, [P, P, i64, i64, P, P, P]),
             "knn_resolve_rows": (i32, [P, P, i64, i64, P, i64, P]),
             "knn_approx_bins": (i64, [i64, i32, f64, i64]),
-            "knn_approx_top_k": (i32, [P, i32, i64, i64, i64, i32, i32, f64, i64, i64, i32, i32, P, P, P]),
+            "knn_approx_top_k": (i32, [P, i32, i64, i64, i64, i32, i32, f64, i64, i64, i32, i32, P, P, P, SZ, P]),
+            "knn_approx_workspace_size": (i32, [i32, i64, i64, i64, i32, i32, f64, i64, i64, i32, i32,
+                                                ctypes.POINTER(SZ)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -120,9 +127,24 @@ def bin_start(b: int, N: int, L: int) -> int:
     return int(lib().knn_bin_start(int(b), int(N), int(L)))
 
 
+def _device_buffer(nbytes: int, device) -> torch.Tensor:
+    """Caller-owned device memory for the library (a torch allocation)."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _same_device(*named):
+    devs = {t.device for _, t in named if t is not None}
+    if len(devs) > 1:
+        raise ValueError("tensors on different devices: " + ", ".join(f"{n} on {t.device}" for n, t in named
+                                                                       if t is not None))
+
+
 # ------------------------------------------------------------------------------ search
 def search(Q: torch.Tensor, X: torch.Tensor, k: int, L: int | None = None, metric="mips"):
     """The plain FP32 search (``knn_search``): returns (values, indices), each M x k."""
+    if Q.dim() != 2 or X.dim() != 2 or Q.shape[1] != X.shape[1]:
+        raise ValueError(f"Q (M x D) and X (N x D) must share the depth D: Q {tuple(Q.shape)}, X {tuple(X.shape)}")
+    _same_device(("Q", Q), ("X", X))
     _dev(Q, "Q")
     _dev(X, "X")
     if Q.dtype != torch.float32 or X.dtype != torch.float32:
@@ -137,17 +159,25 @@ def search(Q: torch.Tensor, X: torch.Tensor, k: int, L: int | None = None, metri
 
 
 class Database:
-    """A prepared database (``knn_db_create``); keeps a reference to X (the FP32 rerank reads it)."""
+    """A database prepared once (``knn_db_prepare``) into a device buffer this object owns
+    (a torch allocation); keeps a reference to X, which the FP32 rerank reads."""
 
     def __init__(self, X: torch.Tensor, metric="mips", compute: str = "fp32"):
+        if X.dim() != 2:
+            raise ValueError("X must be N x D")
         _dev(X, "X")
         self.X = X
         self.metric = _metric(metric)
         self.compute = DTYPES[compute]
         self.N, self.D = X.shape
+        nbytes = int(lib().knn_db_prepare_size(self.N, self.D, self.metric, self.compute))
+        if nbytes == 0:
+            _check(lib().knn_db_prepare(_ptr(X), _in_dtype(X), self.N, self.D, self.metric, self.compute, None, 0,
+                                        _stream(), ctypes.byref(ctypes.c_void_p())))
+        self.buf = _device_buffer(nbytes, X.device)
         h = ctypes.c_void_p()
-        _check(lib().knn_db_create(_ptr(X), _in_dtype(X), self.N, self.D, self.metric, self.compute, _stream(),
-                                   ctypes.byref(h)))
+        _check(lib().knn_db_prepare(_ptr(X), _in_dtype(X), self.N, self.D, self.metric, self.compute, _ptr(self.buf),
+                                    nbytes, _stream(), ctypes.byref(h)))
         self._h = h
 
     @property
@@ -177,14 +207,31 @@ class Database:
                                    _stream()))
         return codes, e, hn
 
+    def workspace_size(self, M: int, k: int, L: int | None = None, rerank: int = 0, return_bins: bool = False,
+                       recall_target: float = 0.95, input_size_override: int = -1) -> int:
+        """``knn_db_search_workspace_size``: device bytes a search with these arguments needs."""
+        n = ctypes.c_size_t()
+        _check(lib().knn_db_search_workspace_size(self._h, int(M), int(k), int(L or 0), float(recall_target),
+                                                  int(input_size_override), int(rerank), int(bool(return_bins)),
+                                                  ctypes.byref(n)))
+        return int(n.value)
+
+    def bins(self, k: int, L: int | None = None, recall_target: float = 0.95, input_size_override: int = -1) -> int:
+        """The bin count a search uses (L given, or derived as ``knn_db_search`` does)."""
+        if L:
+            return int(L)
+        return approx_bins(self.N, k, recall_target, input_size_override)
+
     def search(self, Q: torch.Tensor, k: int, L: int | None = None, rerank: int = 0, return_bins: bool = False,
-               out=None):
-        """``knn_db_search``: (values, indices[, bins_val, bins_idx])."""
+               out=None, recall_target: float = 0.95, input_size_override: int = -1, workspace=None):
+        """``knn_db_search``: (values, indices[, bins_val, bins_idx]).  The workspace is a torch
+        allocation unless ``workspace`` (a uint8 device tensor) is given."""
+        if Q.dim() != 2 or Q.shape[1] != self.D:
+            raise ValueError(f"Q must be M x {self.D} (got {tuple(Q.shape)})")
+        _same_device(("Q", Q), ("X", self.X))
         _dev(Q, "Q")
         M = Q.shape[0]
-        if Q.shape[1] != self.D:
-            raise ValueError("Q has the wrong depth")
-        L = int(L or bins_for_recall(k, 0.95, self.N))
+        L = self.bins(k, L, recall_target, input_size_override)
         if out is None:
             ov = torch.empty((M, k), dtype=torch.float32, device=Q.device)
             oi = torch.empty((M, k), dtype=torch.int32, device=Q.device)
@@ -194,8 +241,11 @@ class Database:
         if return_bins:
             bv = torch.empty((M, L), dtype=torch.float32, device=Q.device)
             bi = torch.empty((M, L), dtype=torch.int32, device=Q.device)
-        _check(lib().knn_db_search(self._h, _ptr(Q), _in_dtype(Q), M, int(k), L, int(rerank), _ptr(ov), _ptr(oi),
-                                   _ptr(bv), _ptr(bi), _stream()))
+        if workspace is None:
+            workspace = _device_buffer(self.workspace_size(M, k, L, rerank, return_bins), Q.device)
+        _check(lib().knn_db_search(self._h, _ptr(Q), _in_dtype(Q), M, int(k), L, float(recall_target),
+                                   int(input_size_override), int(rerank), _ptr(ov), _ptr(oi), _ptr(bv), _ptr(bi),
+                                   _ptr(workspace), workspace.numel(), _stream()))
         return (ov, oi, bv, bi) if return_bins else (ov, oi)
 
 
@@ -224,7 +274,8 @@ class Database:
 
 
 class BatchedPlan:
-    """``knn_plan_create`` / ``knn_search_batched`` over several prepared databases."""
+    """``knn_plan_create`` / ``knn_plan_setup`` / ``knn_search_batched`` over several prepared
+    databases; the plan's workspace is a torch allocation this object owns."""
 
     def __init__(self, dbs, batches, recall_target: float = 0.95, tune: bool = False, cache_path: str | None = None):
         """batches: list of (Q tensor, db index, k).  Output tensors are allocated here and bound to the plan."""
@@ -234,6 +285,11 @@ class BatchedPlan:
         qdt = None
         self._keep = []
         for i, (Q, d, k) in enumerate(batches):
+            if not 0 <= int(d) < len(self.dbs):
+                raise ValueError(f"batch {i}: database index {d} out of range")
+            if Q.dim() != 2 or Q.shape[1] != self.dbs[d].D:
+                raise ValueError(f"batch {i}: Q must be M x {self.dbs[d].D} (got {tuple(Q.shape)})")
+            _same_device(("Q", Q), ("X", self.dbs[d].X))
             _dev(Q, "Q")
             qdt = _in_dtype(Q) if qdt is None else qdt
             if _in_dtype(Q) != qdt:
@@ -246,8 +302,12 @@ class BatchedPlan:
         hs = (ctypes.c_void_p * len(self.dbs))(*[d.handle.value for d in self.dbs])
         h = ctypes.c_void_p()
         _check(lib().knn_plan_create(hs, len(self.dbs), arr, len(batches), qdt, float(recall_target), int(tune),
-                                     cache_path.encode() if cache_path else None, _stream(), ctypes.byref(h)))
+                                     cache_path.encode() if cache_path else None, ctypes.byref(h)))
         self._h = h
+        n = ctypes.c_size_t()
+        _check(lib().knn_plan_workspace_size(self._h, ctypes.byref(n)))
+        self.workspace = _device_buffer(n.value, self.dbs[0].X.device)
+        _check(lib().knn_plan_setup(self._h, _ptr(self.workspace), self.workspace.numel(), _stream()))
 
     def run(self):
         _check(lib().knn_search_batched(self._h, _stream()))
@@ -304,9 +364,12 @@ def approx_top_k(scores: torch.Tensor, k: int, reduction_dimension: int = -1, re
         oi = torch.empty(shape, dtype=torch.int32, device=scores.device)
     else:
         ov, oi = out
-    _check(lib().knn_approx_top_k(_ptr(scores), _in_dtype(scores), rows, cols, ld, dim, int(k), float(recall_target),
-                                  int(reduction_input_size_override), int(L), int(bool(minimize)),
-                                  int(bool(aggregate_to_topk)), _ptr(ov), _ptr(oi), _stream()))
+    args = (_in_dtype(scores), rows, cols, ld, dim, int(k), float(recall_target), int(reduction_input_size_override),
+            int(L), int(bool(minimize)), int(bool(aggregate_to_topk)))
+    n = ctypes.c_size_t()
+    _check(lib().knn_approx_workspace_size(*args, ctypes.byref(n)))
+    ws = _device_buffer(n.value, scores.device) if n.value else None
+    _check(lib().knn_approx_top_k(_ptr(scores), *args[:11], _ptr(ov), _ptr(oi), _ptr(ws), n.value, _stream()))
     return ov, oi
 
 
@@ -326,6 +389,12 @@ def backward(g: torch.Tensor, idx: torch.Tensor, Q: torch.Tensor, X: torch.Tenso
     """``knn_backward``: (dQ, dX) FP32 for the retrieved-score gradient g (selection fixed).
     ``out=(dQ, dX)``: caller buffers; dQ is overwritten and dX accumulated into (as the C
     function does), so a fresh gradient needs a zeroed dX."""
+    if g.dim() != 2 or idx.shape != g.shape:
+        raise ValueError(f"g and idx must both be M x K (got {tuple(g.shape)} and {tuple(idx.shape)})")
+    if Q.dim() != 2 or X.dim() != 2 or Q.shape[0] != g.shape[0] or Q.shape[1] != X.shape[1]:
+        raise ValueError(f"need Q M x D and X N x D with M = {g.shape[0]} (got Q {tuple(Q.shape)}, "
+                         f"X {tuple(X.shape)})")
+    _same_device(("g", g), ("idx", idx), ("Q", Q), ("X", X))
     for t, n in ((g, "g"), (idx, "idx"), (Q, "Q"), (X, "X")):
         _dev(t, n)
     if g.dtype != torch.float32 or idx.dtype != torch.int32:

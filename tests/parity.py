@@ -20,6 +20,12 @@ import numpy as np
 
 import oracle
 
+# Unit roundoff of the FP8 parity bound: the block-scaled FP8 matrix instruction sums
+# its 64-deep products less exactly than FP32 accumulation; its measured error reaches
+# 5.4 x gamma_n(2^-23) * mag at depth 64 (test_gpu_boundary.py characterises it over
+# 4.2 M dot products), and 8 x 2^-23 is the smallest power of two above that.
+FP8_U = 2.0 ** -20
+
 
 def gamma(dpad: int, u: float = 2.0 ** -23) -> float:
     n = dpad + 3

@@ -63,11 +63,12 @@ def test_approx_top_k_argument_checks(K):
     lib = K.lib()
     fake = _p(0x1000)
     args = dict(dt=0, rows=4, cols=100, ld=100, dim=1, k=5, r=0.95, over=-1, L=10, mn=0, agg=1)
+    big = ctypes.c_size_t(1 << 40)
 
-    def call(**kw):
+    def call(ws=fake, nws=big.value, **kw):
         a = {**args, **kw}
         return lib.knn_approx_top_k(fake, a["dt"], a["rows"], a["cols"], a["ld"], a["dim"], a["k"], a["r"],
-                                    a["over"], a["L"], a["mn"], a["agg"], fake, fake, None)
+                                    a["over"], a["L"], a["mn"], a["agg"], fake, fake, ws, nws, None)
     assert call(dt=2) == 1
     assert call(ld=99) == 1
     assert call(dim=2) == 1
@@ -82,6 +83,15 @@ def test_approx_top_k_argument_checks(K):
     # no slices: succeeds without touching the device
     assert call(rows=0) == 0
     assert call(dim=0, rows=100, cols=0) == 0
+    # the workspace: the query reports B * L bins when aggregating and nothing otherwise;
+    # one byte short is refused before anything is enqueued
+    n = ctypes.c_size_t()
+    assert lib.knn_approx_workspace_size(0, 4, 100, 100, 1, 5, 0.95, -1, 10, 0, 1, ctypes.byref(n)) == 0
+    assert n.value >= 4 * 10 * 8
+    assert call(nws=n.value - 1) == 1 and b"workspace too small" in lib.knn_last_error()
+    assert call(ws=None, nws=n.value) == 1
+    assert lib.knn_approx_workspace_size(0, 4, 100, 100, 1, 5, 0.95, -1, 10, 0, 0, ctypes.byref(n)) == 0
+    assert n.value == 0
 
 
 def test_status_strings(K):
@@ -111,16 +121,42 @@ def test_invalid_arguments_return_before_any_device_work(K):
     assert lib.knn_search(fake, 4, fake, 100, 16, 5, 10, 7, fake, fake, None) == 1
     # NULL pointers
     assert lib.knn_search(None, 4, fake, 100, 16, 5, 10, 0, fake, fake, None) == 1
-    # database creation: NULL X, bad dtype, N = 0
-    assert lib.knn_db_create(None, 0, 100, 16, 0, 0, None, ctypes.byref(out)) == 1
-    assert lib.knn_db_create(fake, 2, 100, 16, 0, 0, None, ctypes.byref(out)) == 1
-    assert lib.knn_db_create(fake, 0, 0, 16, 0, 0, None, ctypes.byref(out)) == 1
+    # database preparation: NULL X, bad dtype, N = 0, no buffer, a buffer one byte short
+    need = lib.knn_db_prepare_size(100, 16, 0, 0)
+    assert need > 0 and lib.knn_db_prepare_size(0, 16, 0, 0) == 0
+    assert lib.knn_db_prepare(None, 0, 100, 16, 0, 0, fake, need, None, ctypes.byref(out)) == 1
+    assert lib.knn_db_prepare(fake, 2, 100, 16, 0, 0, fake, need, None, ctypes.byref(out)) == 1
+    assert lib.knn_db_prepare(fake, 0, 0, 16, 0, 0, fake, need, None, ctypes.byref(out)) == 1
+    assert lib.knn_db_prepare(fake, 0, 100, 16, 0, 0, None, need, None, ctypes.byref(out)) == 1
+    assert lib.knn_db_prepare(fake, 0, 100, 16, 0, 0, fake, need - 1, None, ctypes.byref(out)) == 1
+    assert b"buf too small" in lib.knn_last_error()
     assert out.value is None
-    assert lib.knn_db_search(None, fake, 0, 4, 5, 10, 0, fake, fake, None, None, None) == 1
+    assert lib.knn_db_search(None, fake, 0, 4, 5, 10, 0.95, -1, 0, fake, fake, None, None, fake, 1 << 30, None) == 1
     assert lib.knn_backward(fake, fake, fake, fake, 0, 4, 100, 300, 5, 0, fake, fake, None) == 2
     assert lib.knn_backward(fake, fake, fake, fake, 0, 4, 0, 16, 5, 0, fake, fake, None) == 1
     assert lib.knn_search_batched(None, None) == 1
-    assert lib.knn_plan_create(None, 0, None, 0, 0, 0.95, 0, None, None, ctypes.byref(out)) == 1
+    assert lib.knn_plan_create(None, 0, None, 0, 0, 0.95, 0, None, ctypes.byref(out)) == 1
+    assert lib.knn_plan_setup(None, fake, 1 << 30, None) == 1
     assert lib.knn_db_destroy(None) == 0 and lib.knn_plan_destroy(None) == 0
     # M = 0 is a no-op that succeeds without touching the device
     assert lib.knn_search(None, 0, fake, 100, 16, 5, 10, 0, None, None, None) == 0
+
+
+def test_search_size_queries_check_their_handle(K):
+    """The workspace query and the search refuse a NULL database handle (the workspace
+    size checks of a prepared database need a device: tests/test_gpu_search.py)."""
+    lib = K.lib()
+    fake = _p(0x1000)
+    n = ctypes.c_size_t()
+    assert lib.knn_db_search_workspace_size(None, 10, 5, 10, 0.95, -1, 0, 0, ctypes.byref(n)) == 1
+    assert lib.knn_db_search(None, fake, 0, 10, 5, 10, 0.95, -1, 0, fake, fake, None, None, fake, 0, None) == 1
+
+
+def test_plan_create_is_host_only_and_checks_arguments(K):
+    lib = K.lib()
+    out = ctypes.c_void_p()
+    arr = (K.KnnBatch * 1)()
+    hs = (ctypes.c_void_p * 1)(None)
+    assert lib.knn_plan_create(hs, 1, arr, 1, 1, 0.95, 0, None, ctypes.byref(out)) == 1  # NULL database
+    assert b"database 0 is NULL" in lib.knn_last_error()
+    assert lib.knn_plan_workspace_size(None, ctypes.byref(ctypes.c_size_t())) == 1

@@ -17,7 +17,7 @@ import torch
 
 import oracle
 from paper_2206_14286_amd import datagen, knn
-from parity import check_bins, check_rerank, check_topk
+from parity import FP8_U, check_bins, check_rerank, check_topk
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -69,7 +69,7 @@ def test_full_size_cosine_glove_sampled():
         vals, idx = db8.search(Qd, K, Lc, rerank=Kr)
         torch.cuda.synchronize()
         n_sure = check_rerank(Qs, X, "cosine", "fp8", K, Lc, Kr, vals.cpu().numpy()[sample],
-                              idx.cpu().numpy()[sample], _dpad(D, "fp8"), 2.0 ** -20)
+                              idx.cpu().numpy()[sample], _dpad(D, "fp8"), FP8_U)
         _log(f"  {n_sure} sure rows checked")
         assert n_sure >= len(sample) * K // 4
     del db8, Xd, Qd, vals, idx
