@@ -168,6 +168,21 @@ knn_status knn_db_search_workspace_size(const knn_db* db, int64_t M, int32_t K, 
                                         int64_t input_size_override, int32_t rerank_k, int32_t with_bins,
                                         size_t* bytes);
 
+/* knn_db_search for callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation): the same arguments
+ * without the workspace, which comes instead from a fixed device array of
+ * knn_noalloc_scratch_bytes() bytes (32 MiB) that the library holds on every device it
+ * runs on until the process ends.  A search whose workspace would exceed it
+ * (knn_db_search_workspace_size) returns KNN_ERR_INVALID with nothing enqueued.  No
+ * allocation, no synchronisation; the stream must belong to the current device.  All
+ * calls on one device share that array, so calls that overlap in time on one device
+ * (other streams, other threads) race: order them on one stream. */
+knn_status knn_db_search_noalloc(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, int32_t K, int64_t L,
+                                 double recall_target, int64_t input_size_override, int32_t rerank_k,
+                                 float* out_val, int32_t* out_idx, float* bins_val, int32_t* bins_idx,
+                                 void* stream);
+size_t knn_noalloc_scratch_bytes(void);
+
 /* The two steps of a search exposed on their own, for callers that reuse prepared
  * queries and for timing the distance kernel alone.
  * knn_query_buffer_bytes: size of the device buffer knn_query_prepare fills for M queries.

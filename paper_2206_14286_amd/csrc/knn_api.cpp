@@ -532,6 +532,59 @@ extern "C" knn_status knn_search(const float* Q, int64_t M, const float* X, int6
                      static_cast<unsigned char*>(tmp.p) + tiles_bytes, s);
 }
 
+// --------------------------------------------------------------------------- allocation-free search
+namespace {
+
+// Fixed device scratch of knn_db_search_noalloc: the search's workspace for callers that
+// cannot allocate.  Each device the library runs on holds its own copy until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device memory: its
+// device address is looked up per device (hipGetSymbolAddress) and only that is used.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+knn_status scratch_of_current_device(unsigned char** out) {
+  static std::mutex mu;
+  static std::map<int, unsigned char*> addr;  // device -> address of its copy
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress (scratch)");
+    it = addr.emplace(dev, static_cast<unsigned char*>(p)).first;
+  }
+  *out = it->second;
+  return KNN_OK;
+}
+
+}  // namespace
+
+extern "C" size_t knn_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" knn_status knn_db_search_noalloc(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, int32_t K,
+                                            int64_t L, double recall_target, int64_t input_size_override,
+                                            int32_t rerank_k, float* out_val, int32_t* out_idx, float* bins_val,
+                                            int32_t* bins_idx, void* stream) {
+  g_last_error.clear();
+  if (!db) return fail(KNN_ERR_INVALID, "db is NULL");
+  L = resolve_bins(db->N, K, L, recall_target, input_size_override);
+  if (L < 1) return fail(KNN_ERR_INVALID, "cannot derive L (K=%d, recall_target=%g)", K, recall_target);
+  knn_status st = check_search(db, Q, q_dtype, M, K, L, rerank_k, out_val, out_idx, bins_val, bins_idx);
+  if (st != KNN_OK) return st;
+  const size_t need = search_layout(db, M, L, rerank_k, bins_val != nullptr).total;
+  if (need > kScratchBytes)
+    return fail(KNN_ERR_INVALID,
+                "this search needs %zu bytes of scratch, more than the fixed %zu of knn_db_search_noalloc "
+                "(fewer queries per call, fewer bins, a smaller rerank_k, or knn_db_search with a workspace)",
+                need, kScratchBytes);
+  if (M == 0) return KNN_OK;
+  unsigned char* ws = nullptr;
+  st = scratch_of_current_device(&ws);
+  if (st != KNN_OK) return st;
+  return search_core(db, Q, q_dtype, M, K, L, rerank_k, out_val, out_idx, bins_val, bins_idx, ws, (hipStream_t)stream);
+}
+
 // --------------------------------------------------------------------------- separate steps
 static int64_t query_tiles_for(int64_t M) {
   // padded to the widest query block (kWaves * 32 * 2 queries) so any ncb can read it

@@ -57,6 +57,8 @@ def lib():
             "knn_search": (i32, [P, i64, P, i64, i32, i32, i64, i32, P, P, P]),
             "knn_db_search": (i32, [P, P, i32, i64, i32, i64, f64, i64, i32, P, P, P, P, P, SZ, P]),
             "knn_db_search_workspace_size": (i32, [P, i64, i32, i64, f64, i64, i32, i32, ctypes.POINTER(SZ)]),
+            "knn_db_search_noalloc": (i32, [P, P, i32, i64, i32, i64, f64, i64, i32, P, P, P, P, P]),
+            "knn_noalloc_scratch_bytes": (SZ, []),
             "knn_plan_create": (i32, [ctypes.POINTER(P), i32, ctypes.POINTER(KnnBatch), i32, i32, f64, i32,
                                       ctypes.c_char_p, ctypes.POINTER(P)]),
             "knn_plan_workspace_size": (i32, [P, ctypes.POINTER(SZ)]),
