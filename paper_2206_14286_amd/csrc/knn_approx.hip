@@ -91,7 +91,7 @@ __device__ __forceinline__ float piece_elem(const u32x4& u, int i) {
 template <typename T, bool ALIGNED, bool MIN>
 __global__ __launch_bounds__(kApproxThreads) void approx_rows_kernel(const T* __restrict__ S, int64_t B, int64_t n,
                                                                      int64_t ld, int64_t L, int64_t bpi,
-                                                                     int64_t ipr, double l_over_n,
+                                                                     int64_t ipr, uint32_t l_mul,
                                                                      float* __restrict__ outV,
                                                                      int32_t* __restrict__ outA) {
   constexpr int VEC = 16 / sizeof(T);  // scores per piece
@@ -108,7 +108,6 @@ __global__ __launch_bounds__(kApproxThreads) void approx_rows_kernel(const T* __
   // conflicts (16 consecutive lanes cover all 16 16-byte bank groups).
   const int perm = 4 * (lane & 15) + (lane >> 4);
   const int rd = 64 * (lane >> 4) + (lane & 15);
-  const double inv_n = 1.0 / (double)n;
   const int64_t n_items = B * ipr;
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const int64_t r = it / ipr;
@@ -127,7 +126,10 @@ __global__ __launch_bounds__(kApproxThreads) void approx_rows_kernel(const T* __
     // leave the current bin (hand its winner to the slot) and enter the bin of j
     auto enter = [&](int32_t j) {
       if (cb >= 0) atomicMax(&slot[cb], win_key<MIN>(bv, bj));
-      int64_t be = (int64_t)(((double)j + 1.0) * l_over_n - inv_n) - b0;  // off by <= 1
+      // bin of j is floor(((j+1) L - 1) / n); l_mul = floor(2^32 L / n) gives
+      // floor((j+1) L / n) or one less (one 32 x 32 -> 64-bit multiply, no division),
+      // within 2 of it; the two loops below make it exact
+      int64_t be = (int64_t)(((uint64_t)(uint32_t)(j + 1) * l_mul) >> 32) - b0;
       int b = (int)(be < 0 ? 0 : (be >= nb ? nb - 1 : be));
       while (b > 0 && start[b] > j) --b;
       while (start[b + 1] <= j) ++b;
@@ -320,12 +322,14 @@ void launch_rows(const T* S, int64_t B, int64_t n, int64_t ld, int64_t L, float*
   }
   const int64_t ipr = (L + bpi - 1) / bpi;
   const unsigned grid = grid_for(B * ipr);
-  const double l_over_n = (double)L / (double)n;
+  // floor(2^32 L / n), saturated at L = n: a fixed-point L / n for the bin estimate
+  const uint64_t lm = (uint64_t)(((unsigned __int128)L << 32) / (unsigned __int128)n);
+  const uint32_t l_mul = lm > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)lm;
   const bool aligned = (reinterpret_cast<uintptr_t>(S) % 16 == 0) && ((ld * (int64_t)sizeof(T)) % 16 == 0);
   if (aligned)
-    approx_rows_kernel<T, true, MIN><<<grid, kApproxThreads, 0, s>>>(S, B, n, ld, L, bpi, ipr, l_over_n, outV, outA);
+    approx_rows_kernel<T, true, MIN><<<grid, kApproxThreads, 0, s>>>(S, B, n, ld, L, bpi, ipr, l_mul, outV, outA);
   else
-    approx_rows_kernel<T, false, MIN><<<grid, kApproxThreads, 0, s>>>(S, B, n, ld, L, bpi, ipr, l_over_n, outV, outA);
+    approx_rows_kernel<T, false, MIN><<<grid, kApproxThreads, 0, s>>>(S, B, n, ld, L, bpi, ipr, l_mul, outV, outA);
 }
 
 template <typename T, bool MIN>

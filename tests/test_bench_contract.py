@@ -59,10 +59,55 @@ def test_perf_model_rows_from_a_bench_line(monkeypatch):
     rows = bench.perf_model_rows(line)
     assert [r["compute"] for r in rows] == ["bf16", "fp32"]
     bf16, fp32 = rows
-    # Sec. 4 with C = 4 for L2: I_COP = 2D/C = 64; BF16 is then bound by the COP ceiling
-    # at the matrix peak (gamma * 64 = 2.52 PFLOP/s), FP32 by its matrix peak
-    assert bf16["I_COP"] == pytest.approx(64.0)
+    # Sec. 4 with the paper's C = 4 for L2: I_COP = 2D/C = 64, so the COP ceiling equals
+    # the matrix peak (gamma * 64 = 2.52 PFLOP/s); the paper's transfer estimate (the
+    # database read once per 256-query block) puts the memory ceiling below both
+    assert bf16["I_COP_paper"] == pytest.approx(64.0)
+    i_mem = 2.0 * 10000 * 1000000 * 128 / (2 * (10000 * 128 + 1000000 * 128 * 10000 / 256) + 8 * 10000 * 176)
+    assert bf16["I_MEM"] == pytest.approx(i_mem, rel=1e-3)
+    assert bf16["ceiling_gflops_paper"] == pytest.approx(min(2516600, 8000 * i_mem), rel=1e-3)
+    assert bf16["bound_paper"] == "memory"
+    # the kernel's ceiling: without counters, C is the kernel's least (1 per score) and
+    # the clock nominal, so the matrix peak binds
+    assert bf16["C_kernel"] == 1.0 and not bf16["C_kernel_measured"] and bf16["bound"] == "matrix"
     assert fp32["bound"] == "matrix"
     assert fp32["ceiling_gflops"] == pytest.approx(157300, rel=1e-6)
     assert bf16["frac_of_ceiling"] == pytest.approx(1400e3 / bf16["ceiling_gflops"])
     assert bf16["I_MEM_measured"] is None  # no counters for these sources
+
+
+def test_perf_model_uses_the_counter_clock_and_measured_c(tmp_path, monkeypatch):
+    """With a counter summary for the current sources the kernel's ceiling takes the
+    measured C and the measured clock: the matrix peak scales by clock / 2.4 GHz."""
+    monkeypatch.setattr(bench, "COUNTERS_FILE", _summary(tmp_path, bench.kernel_source_digest()))
+    line = {"dtype": "bf16", "config": {"M": 10000, "N": 1000000, "D": 128, "L": 176},
+            "roofline": {"achieved": 1400.0}, "variants": {}}
+    (row,) = bench.perf_model_rows(line)
+    assert row["C_kernel"] == 1.5 and row["C_kernel_measured"] and row["clock_ghz"] == 1.8
+    assert row["ceiling_gflops"] == pytest.approx(2516600 * 1.8 / 2.4, rel=1e-3)
+    assert row["I_MEM_measured"] == pytest.approx(2.0 * 10000 * 1000000 * 128 / 123456789, rel=1e-3)
+
+
+def _committed_bench_lines():
+    """Bench lines recorded under profiles/ (a JSON line after a '```json' fence)."""
+    import glob
+    import json
+    out = []
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "bench_*.md"))):
+        text = open(f).read()
+        if "```json" in text:
+            out.append((f, json.loads(text.split("```json", 1)[1].split("```", 1)[0])))
+    return out
+
+
+def test_committed_bench_lines_stay_under_their_ceilings(monkeypatch):
+    """Every performance-model row of a committed bench line, and the rows the current
+    model derives from that line's measurements, has frac_of_ceiling <= 1: the kernel's
+    ceiling (its own C, the clock the counters saw) bounds every measured launch."""
+    lines = _committed_bench_lines()
+    assert lines, "no bench line recorded under profiles/"
+    for f, line in lines:
+        for r in line["perf_model"]:
+            assert r["frac_of_ceiling"] <= 1.0, (f, r["workload"], r["compute"], r["frac_of_ceiling"])
+        for r in bench.perf_model_rows(line):
+            assert r["frac_of_ceiling"] <= 1.0, (f, r["workload"], r["compute"], r["frac_of_ceiling"])
