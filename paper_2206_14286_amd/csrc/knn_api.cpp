@@ -443,6 +443,7 @@ static knn_status search_core(const knn_db* db, const void* Q, int32_t q_dtype, 
   p.n_chunks = lay.n_chunks;
   p.n_qb = (int32_t)lay.n_qb;
   p.out_sign = db->metric == KNN_L2 ? -1.f : 1.f;
+  p.zero_init = db->metric != KNN_L2;
   p.binV = binV;
   p.binA = binA;
   p.ldo = L;
@@ -635,6 +636,7 @@ extern "C" knn_status knn_partial_reduce(const knn_db* db, const void* qbuf, int
   p.n_chunks = ceil_div(L, bpc);
   p.n_qb = (int32_t)n_qb;
   p.out_sign = db->metric == KNN_L2 ? -1.f : 1.f;
+  p.zero_init = db->metric != KNN_L2;
   p.binV = bins_val;
   p.binA = bins_idx;
   p.ldo = L;
@@ -1043,7 +1045,8 @@ double time_group(knn_plan* p, size_t gi, hipStream_t s) {
   fp.bins_per_chunk = g.bins_per_chunk;
   fp.n_chunks = g.n_chunks;
   fp.n_qb = (int32_t)g.n_qb;
-  fp.out_sign = 1.f;
+  fp.out_sign = db->metric == KNN_L2 ? -1.f : 1.f;
+  fp.zero_init = db->metric != KNN_L2;
   fp.binV = g.binV;
   fp.binA = g.binA;
   fp.ldo = g.L;

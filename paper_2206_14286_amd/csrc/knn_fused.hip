@@ -178,13 +178,19 @@ struct TileRegs {
   int sa;
 };
 
-template <int NG>
+// kZ: the accumulators start from zero (MIPS, cosine): the start values are not read
+// and the first matrix instruction takes an inline zero
+template <int NG, bool kZ>
 __device__ __forceinline__ void read_tile(TileRegs<NG>& r, const unsigned char* tile) {
   using G = TileGeom<NG>;
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const float* auxf = reinterpret_cast<const float*>(tile + G::kMainBytes);
+  if constexpr (kZ) {
+    r.init = f32x16{};
+  } else {
 #pragma unroll
-  for (int i = 0; i < 16; ++i) r.init[i] = auxf[h * 16 + i];
+    for (int i = 0; i < 16; ++i) r.init[i] = auxf[h * 16 + i];
+  }
   r.sa = tile[G::kMainBytes + 128 + (lane & 31)];
   // piece (row q, group g, half h) of the swizzled copy: the XOR flips bit 6 (half)
   // and bit 7 (group parity) of the offset inside the row group's block
@@ -299,7 +305,7 @@ __device__ __forceinline__ void mma_tile_interleaved(f32x16 (&acc)[NCB], const T
 // acc[cb] = init + the tile's products, with the A fragments read from LDS in chunks
 // of 4 groups, each chunk's reads issued before the previous chunk's matrix
 // instructions (2 x 4 fragment registers instead of NG).
-template <int DT, int NG, int NCB>
+template <int DT, int NG, int NCB, bool kZ>
 __device__ __forceinline__ void mma_tile_chunked(f32x16 (&acc)[NCB], const unsigned char* tile,
                                                  const u32x4 (&bq)[NCB][NG], const int (&sb)[NCB]) {
   using G = TileGeom<NG>;
@@ -307,9 +313,11 @@ __device__ __forceinline__ void mma_tile_chunked(f32x16 (&acc)[NCB], const unsig
   static_assert(NG % CH == 0 && DT != DT_F32, "chunked form: BF16 / FP8, NG a multiple of 4");
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const float* auxf = reinterpret_cast<const float*>(tile + G::kMainBytes);
-  f32x16 init;
+  f32x16 init = {};
+  if constexpr (!kZ) {
 #pragma unroll
-  for (int i = 0; i < 16; ++i) init[i] = auxf[h * 16 + i];
+    for (int i = 0; i < 16; ++i) init[i] = auxf[h * 16 + i];
+  }
   const int sa = tile[G::kMainBytes + 128 + (lane & 31)];
   const int q = lane & 31, rg = q >> 2, sw = (rg & 3) << 6;
   const int base = rg * NG * 128 + (q & 3) * 16 + ((h << 6) ^ (sw & 64));
@@ -479,7 +487,7 @@ __device__ __forceinline__ BinCursor make_cursor(int64_t b, int64_t N, int64_t L
 
 // kPrio: raise the wave priority while a wave issues a tile's matrix instructions
 // (pays off with three waves per SIMD, costs with two)
-template <int DT, int NG, int NCB, bool kPrio>
+template <int DT, int NG, int NCB, bool kPrio, bool kZ>
 __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_tiles,
                                          const unsigned char* __restrict__ q_tiles, int64_t N, int64_t L, int64_t M,
                                          int64_t q0, int64_t b0, int64_t b1, float sign, float* __restrict__ outV,
@@ -555,6 +563,42 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       }
   };
 
+  auto flush_all = [&]() {  // the current bin is complete: stage it, open the next
+    if constexpr (NCB == 2) {
+      // lane half h stages column block h: it keeps its own half's state of block h
+      // and receives the other half's, in exchange for its state of block 1 - h
+      // (one exchange instead of one per block)
+      float kv = h ? bv[1] : bv[0], sv = h ? bv[0] : bv[1];
+      unsigned ku = h ? bu[1] : bu[0], su = h ? bu[0] : bu[1];
+      const unsigned off = 8u * (unsigned)h;  // group units: the half's first row
+      ku += (ku != kNoUnit && (ku & 1u)) ? off : 0u;
+      su += (su != kNoUnit && (su & 1u)) ? off : 0u;
+      const float ov = __shfl_xor(sv, 32);
+      const unsigned ou = __shfl_xor(su, 32);
+      const bool take = (ov > kv) || (ov == kv && ou < ku);
+      stage_bin<W>(stage, h * 32 + ql, cur_bin, take ? ov : kv, take ? ou : ku, sign);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        bv[cb] = -INFINITY;
+        bu[cb] = kNoUnit;
+      }
+    } else {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        float mv;
+        unsigned mu;
+        merge_halves(bv[cb], bu[cb], h, mv, mu);
+        if (h == (cb & 1)) stage_bin<W>(stage, cb * 32 + ql, cur_bin, mv, mu, sign);
+        bv[cb] = -INFINITY;
+        bu[cb] = kNoUnit;
+      }
+    }
+    if ((cur_bin & (W - 1)) == W - 1 || cur_bin == b1 - 1)
+      drain_window<NCB, W>(stage, cur_bin & ~(W - 1), (int)b0, (int)b1, outV, outA, ldo, wq0, M, vec_ok, lane);
+    ++cur_bin;
+    cursor.advance();
+  };
+
   // Everything after a tile's scores are folded into (nbv, nbu): the fast path,
   // the one-boundary masked path and the row walk, bin flushes.
   auto finish = [&](int t0, f32x16 (&acc_c)[NCB], float (&nbv)[NCB], unsigned (&nbu)[NCB]) {
@@ -576,41 +620,6 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       bv[cb] = fast ? nbv[cb] : bv[cb];
       bu[cb] = fast ? nbu[cb] : bu[cb];
     }
-    auto flush_all = [&]() {  // the current bin is complete: stage it, open the next
-      if constexpr (NCB == 2) {
-        // lane half h stages column block h: it keeps its own half's state of block h
-        // and receives the other half's, in exchange for its state of block 1 - h
-        // (one exchange instead of one per block)
-        float kv = h ? bv[1] : bv[0], sv = h ? bv[0] : bv[1];
-        unsigned ku = h ? bu[1] : bu[0], su = h ? bu[0] : bu[1];
-        const unsigned off = 8u * (unsigned)h;  // group units: the half's first row
-        ku += (ku != kNoUnit && (ku & 1u)) ? off : 0u;
-        su += (su != kNoUnit && (su & 1u)) ? off : 0u;
-        const float ov = __shfl_xor(sv, 32);
-        const unsigned ou = __shfl_xor(su, 32);
-        const bool take = (ov > kv) || (ov == kv && ou < ku);
-        stage_bin<W>(stage, h * 32 + ql, cur_bin, take ? ov : kv, take ? ou : ku, sign);
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          bv[cb] = -INFINITY;
-          bu[cb] = kNoUnit;
-        }
-      } else {
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          float mv;
-          unsigned mu;
-          merge_halves(bv[cb], bu[cb], h, mv, mu);
-          if (h == (cb & 1)) stage_bin<W>(stage, cb * 32 + ql, cur_bin, mv, mu, sign);
-          bv[cb] = -INFINITY;
-          bu[cb] = kNoUnit;
-        }
-      }
-      if ((cur_bin & (W - 1)) == W - 1 || cur_bin == b1 - 1)
-        drain_window<NCB, W>(stage, cur_bin & ~(W - 1), (int)b0, (int)b1, outV, outA, ldo, wq0, M, vec_ok, lane);
-      ++cur_bin;
-      cursor.advance();
-    };
     if (fast) {
       if (t0 + 32 == cursor.next32) flush_all();  // the bin ends with this tile
       return;
@@ -756,8 +765,15 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       // a wave issuing its matrix instructions goes first, so the SIMD's other waves
       // fill the gaps with their bin updates instead of delaying the matrix unit
       if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
-      mma_tile_chunked<DT, NG, NCB>(acc, buf(t), bq, sb);
+      mma_tile_chunked<DT, NG, NCB, kZ>(acc, buf(t), bq, sb);
       if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
+      // a tile inside the item and inside the current bin (the common case, a uniform
+      // test) folds its scores into the running state in place
+      if (t0 >= r0 && t0 + 32 <= r1 && t0 + 32 <= cursor.next32) {
+        static_for<0, 2 * NCB>([&](auto pc) { unit_pair(pc, acc, bv, bu, gu0); });
+        if (t0 + 32 == cursor.next32) flush_all();  // the bin ends with this tile
+        continue;
+      }
       float nbv[NCB];
       unsigned nbu[NCB];
 #pragma unroll
@@ -782,7 +798,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     if (t_last - t_first >= S - 1) wait_vmcnt<(S - 1) * G::kLoads>(); else wait_vmcnt<0>();
     lds_barrier();
     if (active) {
-      read_tile<NG>(fr, buf(t_first));
+      read_tile<NG, kZ>(fr, buf(t_first));
       mma_tile<DT, NG, NCB>(acc_a, fr, bq, sb);
     }
     auto step = [&](int t, f32x16 (&acc_c)[NCB], f32x16 (&acc_n)[NCB]) {
@@ -803,7 +819,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
         nbv[cb] = bv[cb];
         nbu[cb] = bu[cb];
       }
-      read_tile<NG>(fr, buf(t + 1));
+      read_tile<NG, kZ>(fr, buf(t + 1));
       __builtin_amdgcn_sched_barrier(0);
       mma_tile_interleaved<DT, NG, NCB>(acc_n, fr, bq, sb, [&](auto pc) { unit_pair(pc, acc_c, nbv, nbu, gu0); });
       finish(t0, acc_c, nbv, nbu);
@@ -825,7 +841,7 @@ constexpr int min_waves() {
   return (DT == DT_FP8 && NG == 4) ? 4 : (((DT == DT_FP8 && NG < 4) || (DT == DT_BF16 && NG == 8)) ? 3 : 1);
 }
 
-template <int DT, int NG, int NCB>
+template <int DT, int NG, int NCB, bool kZ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<DT, NG>(), 8)))
 void fused_kernel(FusedParams p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -836,28 +852,28 @@ void fused_kernel(FusedParams p) {
   if (chunk >= p.n_chunks) return;
   const int64_t b0 = chunk * p.bins_per_chunk;
   const int64_t b1 = (b0 + p.bins_per_chunk) < p.L ? (b0 + p.bins_per_chunk) : p.L;
-  run_item<DT, NG, NCB, (min_waves<DT, NG>() >= 3)>(p.db_tiles, p.q_tiles, p.N, p.L, p.M, (int64_t)qb * (kWaves * 32 * NCB), b0, b1, p.out_sign, p.binV,
+  run_item<DT, NG, NCB, (min_waves<DT, NG>() >= 3), kZ>(p.db_tiles, p.q_tiles, p.N, p.L, p.M, (int64_t)qb * (kWaves * 32 * NCB), b0, b1, p.out_sign, p.binV,
                         p.binA, p.ldo, lds);
 }
 
-template <int DT, int NG, int NCB>
+template <int DT, int NG, int NCB, bool kZ>
 hipError_t launch_one(const FusedParams& p, hipStream_t s) {
   (void)hipGetLastError();  // clear any stale error so the check below sees this launch only
   const int64_t per_xcd = ceil_div(p.n_chunks, 8);
   const int64_t grid = 8 * per_xcd * p.n_qb;
   constexpr int lb = lds_bytes<DT, NG>();
   {
-    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&fused_kernel<DT, NG, NCB>), lb);
+    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&fused_kernel<DT, NG, NCB, kZ>), lb);
     if (e != hipSuccess) return e;
   }
-  fused_kernel<DT, NG, NCB><<<dim3((unsigned)grid), dim3(64 * kWaves), lb, s>>>(p);
+  fused_kernel<DT, NG, NCB, kZ><<<dim3((unsigned)grid), dim3(64 * kWaves), lb, s>>>(p);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- persistent batched form
 template <int DT, int NG, int NCB>
 __device__ __forceinline__ void run_group_item(const GroupDesc& gd, const WorkItem& it, unsigned char* lds) {
-  run_item<DT, NG, NCB, false>(gd.db_tiles, gd.q_tiles, gd.N, gd.L, gd.M, (int64_t)it.qb * (kWaves * 32 * NCB), it.b0,
+  run_item<DT, NG, NCB, false, false>(gd.db_tiles, gd.q_tiles, gd.N, gd.L, gd.M, (int64_t)it.qb * (kWaves * 32 * NCB), it.b0,
                         it.b1, gd.out_sign, gd.binV, gd.binA, gd.ldo, lds);
 }
 
@@ -928,7 +944,8 @@ bool fused_supported(int dt, int ng, int ncb) {
 hipError_t launch_fused(int dt, int ng, int ncb, const FusedParams& p, hipStream_t s) {
   if (p.M == 0 || p.n_chunks == 0) return hipSuccess;
 #define X(D_, G_, C_) \
-  if (dt == D_ && ng == G_ && ncb == C_) return launch_one<D_, G_, C_>(p, s);
+  if (dt == D_ && ng == G_ && ncb == C_) \
+    return p.zero_init ? launch_one<D_, G_, C_, true>(p, s) : launch_one<D_, G_, C_, false>(p, s);
   KNN_FUSED_CASES(X)
 #undef X
   return hipErrorInvalidValue;

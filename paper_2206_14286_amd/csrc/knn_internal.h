@@ -87,6 +87,7 @@ struct FusedParams {
   float* binV;        // [M x ldo] bin winners in the metric's own sign
   int32_t* binA;
   int64_t ldo;
+  int32_t zero_init;  // the accumulators start from 0 (MIPS, cosine: no half norms)
 };
 // ncb: 32-query column blocks per wave (1 or 2)
 hipError_t launch_fused(int dt, int ng, int ncb, const FusedParams& p, hipStream_t s);
