@@ -382,12 +382,35 @@ __device__ __forceinline__ float max5f(float best, float a0, float a1, float a2,
   return fmaxf(fmaxf(fmaxf(fmaxf(best, a0), a1), a2), a3);
 }
 
+// Exchanges between the two 32-lane halves of a wave with one VALU swap
+// (v_permlane32_swap, no LDS round trip): for x held by every lane, r[0] holds the
+// lower half's values in both halves and r[1] the upper half's.
+__device__ __forceinline__ unsigned other_half(unsigned x, int h) {  // x of lane l ^ 32
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return h ? r[0] : r[1];
+}
+__device__ __forceinline__ float other_half(float x, int h) {
+  return __uint_as_float(other_half(__float_as_uint(x), h));
+}
+__device__ __forceinline__ unsigned lower_half(unsigned x) {  // x of lane l & 31
+  return __builtin_amdgcn_permlane32_swap(x, x, false, false)[0];
+}
+__device__ __forceinline__ unsigned upper_half(unsigned x) {  // x of lane 32 + (l & 31)
+  return __builtin_amdgcn_permlane32_swap(x, x, false, false)[1];
+}
+
+// (value ov, unit ou) beats (v, u): larger value, then lower unit; no short-circuit, so
+// it compiles to straight-line selects
+__device__ __forceinline__ bool beats(float ov, unsigned ou, float v, unsigned u) {
+  return (ov > v) | ((ov == v) & (ou < u));
+}
+
 // merge the two lane halves' (value, unit) of one query: larger value, then lower unit
 __device__ __forceinline__ void merge_halves(float v, unsigned u, int h, float& mv, unsigned& mu) {
   if (u != kNoUnit && (u & 1u)) u += 8u * (unsigned)h;  // group unit: true first row
-  const float ov = __shfl_xor(v, 32);
-  const unsigned ou = __shfl_xor(u, 32);
-  const bool take = (ov > v) || (ov == v && ou < u);
+  const float ov = other_half(v, h);
+  const unsigned ou = other_half(u, h);
+  const bool take = beats(ov, ou, v, u);
   mv = take ? ov : v;
   mu = take ? ou : u;
 }
@@ -573,9 +596,9 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       const unsigned off = 8u * (unsigned)h;  // group units: the half's first row
       ku += (ku != kNoUnit && (ku & 1u)) ? off : 0u;
       su += (su != kNoUnit && (su & 1u)) ? off : 0u;
-      const float ov = __shfl_xor(sv, 32);
-      const unsigned ou = __shfl_xor(su, 32);
-      const bool take = (ov > kv) || (ov == kv && ou < ku);
+      const float ov = other_half(sv, h);
+      const unsigned ou = other_half(su, h);
+      const bool take = beats(ov, ou, kv, ku);
       stage_bin<W>(stage, h * 32 + ql, cur_bin, take ? ov : kv, take ? ou : ku, sign);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
@@ -720,7 +743,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       if (j == cursor.next32) flush_row();
       const int ir = 4 * (jj >> 3) + (jj & 3), hr = (jj >> 2) & 1;  // accumulator and lane half of row jj
       const float a = acc_c[0][ir], b = acc_c[cB][ir];
-      const float other = __shfl_xor(h == 0 ? b : a, 32);
+      const float other = other_half(h == 0 ? b : a, h);
       const float x = hr == h ? (h == 0 ? a : b) : other;
       if (x > sv) {
         sv = x;
@@ -730,13 +753,13 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
     if (hi == cursor.next32) flush_row();
     // back to the per-half form: half 0 carries the open bin's state
     {
-      const float vA = __shfl(sv, ql);
-      const unsigned uA = __shfl(su, ql);
+      const float vA = __uint_as_float(lower_half(__float_as_uint(sv)));
+      const unsigned uA = lower_half(su);
       bv[0] = h == 0 ? vA : -INFINITY;
       bu[0] = h == 0 ? uA : kNoUnit;
       if (NCB == 2) {
-        const float vB = __shfl(sv, 32 + ql);
-        const unsigned uB = __shfl(su, 32 + ql);
+        const float vB = __uint_as_float(upper_half(__float_as_uint(sv)));
+        const unsigned uB = upper_half(su);
         bv[cB] = h == 0 ? vB : -INFINITY;
         bu[cB] = h == 0 ? uB : kNoUnit;
       }
