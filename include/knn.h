@@ -192,12 +192,14 @@ size_t knn_noalloc_scratch_bytes(void);
  * knn_partial_reduce: PartialReduce alone (Sec. 5, Algorithm 1): the M x L bin winners
  *   (bins_val FP32, bins_idx int32, device, row-major), compute-type scores in the
  *   metric's own sign; no top-K (the `aggregate_to_topk = False` form of the paper's op).
- *   bins_idx is in compact form: an entry >= 0 is the winning row; an entry e <= -2
- *   says the winner is one of the 4 rows starting at row 4*(-2-e) (the kernel tracks
- *   the best of each 4-row group of its accumulators); -1 means no finite score.
+ *   bins_idx is in compact form: an entry >= 0 is the winning row; -1 means no finite
+ *   score; smaller entries name a set of rows the winner is among (the kernel tracks
+ *   the best of groups of its accumulators): e > -2 - 2^29: the 4 rows from
+ *   s = 4 (-2 - e); -2 - 2^30 < e <= -2 - 2^29: rows s .. s+3 and s+8 .. s+11 with
+ *   s = 4 (-2 - 2^29 - e); e <= -2 - 2^30: the 16 rows from s = 16 (-2 - 2^30 - e).
  * knn_resolve_rows: replaces every compact entry of idx (M x ncols, leading dimension
- *   ld, row i belonging to query i of qbuf) by the exact row: the 4 rows are rescored
- *   from the prepared rows in FP32 and the best (lowest row on ties) is kept.
+ *   ld, row i belonging to query i of qbuf) by the exact row: the entry's rows are
+ *   rescored from the prepared rows in FP32 and the best (lowest row on ties) is kept.
  *   knn_db_search does this itself; its outputs always hold exact rows. */
 size_t knn_query_buffer_bytes(const knn_db* db, int64_t M);
 knn_status knn_query_prepare(const knn_db* db, const void* Q, int32_t q_dtype, int64_t M, void* qbuf,

@@ -364,14 +364,26 @@ __device__ __forceinline__ void mma_tile_chunked(f32x16 (&acc)[NCB], const unsig
   });
 }
 
-// A bin's running winner is a "unit": either one exact row or a group of 4
-// consecutive rows (one lane's accumulators 4k..4k+3) whose exact row is resolved
-// later from the prepared rows.  Units are keyed u = 2*start + is_group (unsigned,
-// 0xFFFFFFFF = none); units of one bin never overlap, so ordering by u orders by row.
-// Inside a lane, a group unit is kept without the lane half's row offset (4 rows
-// for half 1: the same for all of the lane's groups), so the per-tile update can
-// take it from a scalar; merge_halves adds the offset back.
+// A bin's running winner is a "unit" whose exact row is resolved later from the
+// prepared rows (knn_resolve.hip), keyed by its first row s (unsigned, 0xFFFFFFFF = none):
+//   row    u = 2 s          one exact row
+//   group  u = 2 s + 1      rows s .. s+3 (one lane's accumulators 4k..4k+3)
+//   pair   u = 2 s + 3      rows s .. s+3 and s+8 .. s+11 (a lane's accumulators
+//                           8p..8p+7: two groups, interleaved with the other half's)
+//   quad   u = 2 s + 5      rows s .. s+15 (s a multiple of 16): both halves' pairs
+//                           of one 16-row block, when their best scores tie exactly
+// Units of one bin never share a row, and two units can interleave only as the two
+// halves' pairs of one block (a tie there becomes the quad), so ordering by u orders
+// by lowest row.  Inside a lane, group and pair units are kept without the lane
+// half's row offset (4 rows for half 1: the same for all of the lane's units), so the
+// per-tile update can take them from a scalar; merging the halves adds it back.
 constexpr unsigned kNoUnit = 0xFFFFFFFFu;
+
+// a tie between the halves' pairs of one block becomes that block's quad
+__device__ __forceinline__ unsigned tie_unit(float v0, unsigned u0, float v1, unsigned u1, unsigned take_u) {
+  const bool quad = (v0 == v1) & ((u0 & 7u) == 3u) & ((u1 & 7u) == 3u) & ((u0 >> 5) == (u1 >> 5));
+  return quad ? ((u0 & ~31u) | 5u) : take_u;
+}
 
 // max(best, a0..a3) folded left to right, which the compiler turns into two v_max3_f32:
 // max3(max3(best, a0, a1), a2, a3).  (Nested the other way, it computes the group's
@@ -412,14 +424,18 @@ __device__ __forceinline__ void merge_halves(float v, unsigned u, int h, float& 
   const unsigned ou = other_half(u, h);
   const bool take = beats(ov, ou, v, u);
   mv = take ? ov : v;
-  mu = take ? ou : u;
+  mu = tie_unit(ov, ou, v, u, take ? ou : u);
 }
 
-// bins output: value in the metric's sign; row >= 0, or -2 - start/4 for a 4-row group
-// starting at row `start`, or -1 when the bin saw no finite score
+// bins output: value in the metric's sign; a row r >= 0; -2 - s/4 for a group,
+// -2 - 2^29 - s/4 for a pair, -2 - 2^30 - s/16 for a quad starting at row s; -1 when
+// the bin saw no finite score
 __device__ __forceinline__ int32_t bin_code(unsigned u) {
   if (u == kNoUnit) return -1;
-  return (u & 1u) ? -2 - (int32_t)(u >> 3) : (int32_t)(u >> 1);
+  if (!(u & 1u)) return (int32_t)(u >> 1);
+  if ((u & 7u) == 1u) return -2 - (int32_t)(u >> 3);
+  if ((u & 7u) == 3u) return -2 - (1 << 29) - (int32_t)(u >> 3);
+  return -2 - (1 << 30) - (int32_t)(u >> 5);
 }
 
 // put one query's finished bin into the wave's output window
@@ -599,7 +615,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       const float ov = other_half(sv, h);
       const unsigned ou = other_half(su, h);
       const bool take = beats(ov, ou, kv, ku);
-      stage_bin<W>(stage, h * 32 + ql, cur_bin, take ? ov : kv, take ? ou : ku, sign);
+      stage_bin<W>(stage, h * 32 + ql, cur_bin, take ? ov : kv, tie_unit(ov, ou, kv, ku, take ? ou : ku), sign);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         bv[cb] = -INFINITY;
@@ -793,7 +809,20 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       // a tile inside the item and inside the current bin (the common case, a uniform
       // test) folds its scores into the running state in place
       if (t0 >= r0 && t0 + 32 <= r1 && t0 + 32 <= cursor.next32) {
-        static_for<0, 2 * NCB>([&](auto pc) { unit_pair(pc, acc, bv, bu, gu0); });
+        // fold the tile in as pair units: 8 scores per lane per unit, four 3-input
+        // maxima, a compare and a select (a quarter fewer instructions than groups)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+          for (int pp = 0; pp < 2; ++pp) {
+            const f32x16& a = acc[cb];
+            const float n = fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(bv[cb], a[8 * pp]), a[8 * pp + 1]),
+                                                                a[8 * pp + 2]), a[8 * pp + 3]), a[8 * pp + 4]),
+                                              a[8 * pp + 5]), a[8 * pp + 6]), a[8 * pp + 7]);
+            bu[cb] = n > bv[cb] ? gu0 + 2u + 32u * pp : bu[cb];  // pair at row t0 + 16 pp (+ 4 h)
+            bv[cb] = n;
+          }
+        }
         if (t0 + 32 == cursor.next32) flush_all();  // the bin ends with this tile
         continue;
       }

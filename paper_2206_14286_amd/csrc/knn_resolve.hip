@@ -1,14 +1,15 @@
-// knn_resolve.hip -- exact rows for bin winners recorded as 4-row groups.
+// knn_resolve.hip -- exact rows for bin winners recorded as groups of rows.
 //
 // The distance kernel tracks, per lane, the best of each group of 4 accumulators
-// (4 consecutive database rows) instead of the best single accumulator; that
-// halves the per-score instruction count of the bin update.  A winner recorded
-// as a group is resolved here: a group of 16 lanes recomputes the group's 4 scores
-// from the same prepared (converted) rows and query the matrix unit used, in FP32
-// with a fixed order (each lane a strided set of 16-byte pieces, then a butterfly
-// across the 16 lanes), and keeps the best row, the lower row on ties.  The result can differ from the
-// matrix unit's choice only when two rows of the group score within rounding of
-// each other.
+// (4 consecutive database rows), or of each pair of such groups, instead of the best
+// single accumulator; that cuts the per-score instruction count of the bin update.
+// A winner recorded as a group (4 rows), a pair (rows s..s+3 and s+8..s+11) or a
+// quad (16 consecutive rows) is resolved here: a group of 16 lanes recomputes the
+// scores of each 4-row block, in increasing row order, from the same prepared
+// (converted) rows and query the matrix unit used, in FP32 with a fixed order (each
+// lane a strided set of 16-byte pieces, then a butterfly across the 16 lanes), and
+// keeps the best row, the lower row on ties.  The result can differ from the matrix
+// unit's choice only when two rows score within rounding of each other.
 #include "knn_common.cuh"
 
 namespace knn {
@@ -55,44 +56,62 @@ __device__ __forceinline__ void resolve16(int32_t* p, const unsigned char* __res
                                           const unsigned char* __restrict__ db_tiles, int ng, int gl) {
   const int32_t code = *p;
   if (code > -2) return;  // already a row (or no winner)
-  const int64_t start = (int64_t)(-2 - code) * 4;
-  const int64_t TB = tile_bytes(ng);
-  const unsigned char* dtile = db_tiles + (start >> 5) * TB;
-  const unsigned char* qtile = q_tiles + (qrow >> 5) * TB;
-  const int r0 = (int)(start & 31), qq = (int)(qrow & 31);
-  float dot[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int pc = gl; pc < 2 * ng; pc += 16) {
-    const int g = pc >> 1, hf = pc & 1;
-    const u32x4 b = *reinterpret_cast<const u32x4*>(qtile + piece_offset(qq, g, hf, ng));
-    const unsigned char* a = dtile + piece_offset(r0, g, hf, ng);  // the 4 rows' pieces are adjacent
-    u32x4 ar[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) ar[r] = *reinterpret_cast<const u32x4*>(a + r * 16);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) dot[r] = piece_dot<DT>(ar[r], b, dot[r]);
+  // the code's 4-row blocks, in increasing row order: (first row, step between blocks, count)
+  int64_t first;
+  int step, nblk;
+  if (code > -2 - (1 << 29)) {  // group
+    first = (int64_t)(-2 - code) * 4;
+    step = 0;
+    nblk = 1;
+  } else if (code > -2 - (1 << 30)) {  // pair
+    first = (int64_t)(-2 - (1 << 29) - code) * 4;
+    step = 8;
+    nblk = 2;
+  } else {  // quad
+    first = (int64_t)(-2 - (1 << 30) - code) * 16;
+    step = 4;
+    nblk = 4;
   }
-#pragma unroll
-  for (int off = 8; off > 0; off >>= 1)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) dot[r] += __shfl_xor(dot[r], off, 16);
+  const int64_t TB = tile_bytes(ng);
+  const unsigned char* dtile = db_tiles + (first >> 5) * TB;  // the blocks share the tile
+  const unsigned char* qtile = q_tiles + (qrow >> 5) * TB;
+  const int qq = (int)(qrow & 31);
   const float* init = reinterpret_cast<const float*>(dtile + ng * 1024);
   float bv = -INFINITY;
-  int best = 0;
+  int64_t best = first;
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int r0 = (int)(first & 31) + blk * step;
+    float dot[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int pc = gl; pc < 2 * ng; pc += 16) {
+      const int g = pc >> 1, hf = pc & 1;
+      const u32x4 b = *reinterpret_cast<const u32x4*>(qtile + piece_offset(qq, g, hf, ng));
+      const unsigned char* a = dtile + piece_offset(r0, g, hf, ng);  // the 4 rows' pieces are adjacent
+      u32x4 ar[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int rr = r0 + r;
-    float d = dot[r];
-    if constexpr (DT == DT_FP8) {
-      const int ea = (int)dtile[ng * 1024 + 128 + rr] - 127, eb = (int)qtile[ng * 1024 + 128 + qq] - 127;
-      d = d * exp2i(ea) * exp2i(eb);
+      for (int r = 0; r < 4; ++r) ar[r] = *reinterpret_cast<const u32x4*>(a + r * 16);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dot[r] = piece_dot<DT>(ar[r], b, dot[r]);
     }
-    const float v = init[((rr >> 2) & 1) * 16 + 4 * (rr >> 3) + (rr & 3)] + d;
-    if (r == 0 || v > bv) {  // strict: the lower row keeps ties
-      bv = v;
-      best = r;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dot[r] += __shfl_xor(dot[r], off, 16);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = r0 + r;
+      float d = dot[r];
+      if constexpr (DT == DT_FP8) {
+        const int ea = (int)dtile[ng * 1024 + 128 + rr] - 127, eb = (int)qtile[ng * 1024 + 128 + qq] - 127;
+        d = d * exp2i(ea) * exp2i(eb);
+      }
+      const float v = init[((rr >> 2) & 1) * 16 + 4 * (rr >> 3) + (rr & 3)] + d;
+      if ((blk == 0 && r == 0) || v > bv) {  // strict, rows in increasing order: the lower row keeps ties
+        bv = v;
+        best = (first & ~(int64_t)31) + rr;
+      }
     }
   }
-  if (gl == 0) *p = (int32_t)(start + best);
+  if (gl == 0) *p = (int32_t)best;
 }
 
 template <int DT>

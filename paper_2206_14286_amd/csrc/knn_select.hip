@@ -22,19 +22,26 @@ constexpr int kMaxK = 1024;
 
 // Scores are keyed by float_key(sgn * v + 0): adding +0 turns -0 into +0, so the two
 // zeros tie as they do under the strict comparison of the bin reduce.
-// Candidate indices are rows (>= 0), 4-row group codes (-2 - start/4, resolved
-// later) or -1 (none).  The tie-break key orders them by row: unit u = 2*start +
-// is_group is unique per candidate (bins are disjoint), and the sort uses ~u so
-// that a lower row ranks first; "none" maps to 0, below every real unit.
+// Candidate indices are rows (>= 0), codes of rows still to be resolved (groups
+// -2 - s/4, pairs -2 - 2^29 - s/4, quads -2 - 2^30 - s/16 for a first row s; see the
+// distance kernel) or -1 (none).  The tie-break key orders them by first row: the unit
+// u = 2 s (+1 group, +3 pair, +5 quad) is unique per candidate (bins are disjoint), and
+// the sort uses ~u so that a lower row ranks first; "none" maps to 0, below every
+// real unit.
 __device__ __forceinline__ unsigned unit_lo(int32_t code) {
   if (code >= 0) return ~(2u * (unsigned)code);
   if (code == -1) return 0u;
-  return ~(2u * 4u * (unsigned)(-2 - code) + 1u);
+  if (code > -2 - (1 << 29)) return ~(8u * (unsigned)(-2 - code) + 1u);
+  if (code > -2 - (1 << 30)) return ~(8u * (unsigned)(-2 - (1 << 29) - code) + 3u);
+  return ~(32u * (unsigned)(-2 - (1 << 30) - code) + 5u);
 }
 __device__ __forceinline__ int32_t unit_code(unsigned lo) {
   if (lo == 0u) return -1;
   const unsigned u = ~lo;
-  return (u & 1u) ? -2 - (int32_t)(u >> 3) : (int32_t)(u >> 1);
+  if (!(u & 1u)) return (int32_t)(u >> 1);
+  if ((u & 7u) == 1u) return -2 - (int32_t)(u >> 3);
+  if ((u & 7u) == 3u) return -2 - (1 << 29) - (int32_t)(u >> 3);
+  return -2 - (1 << 30) - (int32_t)(u >> 5);
 }
 
 struct SelShared {
