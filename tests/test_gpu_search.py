@@ -91,6 +91,42 @@ def test_bins_and_topk_vs_oracle(metric, M, N, D, K, L, compute):
     check_topk(Qq, Xq, mo, K, vals.cpu().numpy(), idx.cpu().numpy(), ora, dp, u=u, value_rtol=rt)
 
 
+LARGE_L_CASES = [
+    # metric, M, N, D, K, L, compute, Kr: more than 1024 bins (the select's histogram
+    # path), searched once with the bins kept internally and once with them returned
+    ("mips", 70, 70000, 128, 10, 2050, "fp32", 0),     # L not a multiple of 16, ragged M
+    ("l2", 300, 40000, 128, 10, 1500, "bf16", 0),      # bins of 26-27 rows
+    ("cosine", 130, 65536, 128, 10, 2048, "fp8", 0),   # bins of 32 rows (small-bin FP8 kernel)
+    ("mips", 257, 50000, 256, 8, 1100, "bf16", 0),     # depth 256
+    ("l2", 129, 30000, 100, 5, 3000, "fp8", 64),       # with the FP32 rerank
+    ("cosine", 40, 20000, 64, 10, 1025, "bf16", 100),  # one bin above the wave-select limit
+    ("mips", 5, 20000, 64, 3, 1500, "fp32", 0),        # fewer rows than one group of 16
+]
+
+
+@pytest.mark.parametrize("metric,M,N,D,K,L,compute,Kr", LARGE_L_CASES)
+def test_large_L_search(metric, M, N, D, K, L, compute, Kr):
+    """A search that keeps its bins internally returns exactly what the same search
+    returns when the caller takes the bins, and the top-K matches the oracle."""
+    _log(f"large L {metric} M={M} N={N} D={D} K={K} L={L} {compute} Kr={Kr}")
+    Q, X = make_inputs(metric, M, N, D, seed=M + N + L)
+    db = knn.Database(to_dev(X), metric, compute)
+    Qd = to_dev(Q)
+    v1, i1 = db.search(Qd, K, L, rerank=Kr)
+    v2, i2, bv, bi = db.search(Qd, K, L, rerank=Kr, return_bins=True)
+    torch.cuda.synchronize()
+    assert torch.equal(i1, i2) and torch.equal(v1, v2)
+    if Kr:
+        return
+    Qq = oracle.quantize_like_library(Q, metric, compute)
+    Xq = oracle.quantize_like_library(X, metric, compute)
+    mo = "mips" if metric == "cosine" else metric
+    ora = oracle.search(Qq, Xq, mo, L, K, bins=True)
+    u, rt = U_BOUND[compute], V_RTOL[compute]
+    check_bins(Qq, Xq, mo, L, bv.cpu().numpy(), bi.cpu().numpy(), ora, dpad_of(D, compute), u=u, value_rtol=rt)
+    check_topk(Qq, Xq, mo, K, v1.cpu().numpy(), i1.cpu().numpy(), ora, dpad_of(D, compute), u=u, value_rtol=rt)
+
+
 @pytest.mark.parametrize("metric,compute", [(m, c) for m in ("mips", "l2", "cosine") for c in ("fp32", "bf16", "fp8")])
 def test_prepared_rows_match_reference_quantisers(metric, compute):
     """The rows the kernel streams are bit-identical to the oracle's quantisers."""
