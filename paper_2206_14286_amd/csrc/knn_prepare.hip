@@ -189,6 +189,89 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void* src, 
                    tiles, orig_half_norm, orig_rnorm);
 }
 
+// Query rows: one wave per row, so that a few queries do not leave one thread per row
+// doing all of its work serially.  Lane l holds elements l, l + 64, ... of the row; for
+// cosine lane 0 sums the squares in dimension order (the same single-rounding sum as
+// prepare_row), the FP8 row maximum is a wave reduction (a maximum in any order is
+// exact), and lane p < 2 NG converts and stores piece p.  Produces the same bytes as
+// prepare_row for a query row (no half norm, init 0).
+constexpr int kQPrepWaves = 4;
+
+template <int CDT>
+__global__ __launch_bounds__(64 * kQPrepWaves) void prepare_queries_kernel(const void* src, int in_dt, int64_t rows,
+                                                                          int D, int ng, int metric,
+                                                                          unsigned char* tiles,
+                                                                          int64_t n_rows_padded) {
+#pragma clang fp contract(off)
+  __shared__ float stage[kQPrepWaves][kMaxDpad];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * kQPrepWaves + w;
+  if (r >= n_rows_padded) return;
+  const bool valid = src != nullptr && r < rows;
+  float* row = stage[w];
+#pragma unroll
+  for (int j = 0; j < kMaxDpad / 64; ++j) {
+    const int d = 64 * j + lane;
+    row[d] = (valid && d < D) ? load_elem(src, in_dt, r * (int64_t)D + d) : 0.f;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const bool cosine = metric == MET_COSINE;
+  float nrm = 0.f;
+  if (cosine) {
+    float ss = 0.f;
+    if (lane == 0)
+      for (int d = 0; d < D; ++d) ss = ss + row[d] * row[d];
+    nrm = sqrtf(__shfl(ss, 0));  // correctly rounded square root (HIP default)
+  }
+  auto get = [&](int d) -> float {
+    const float x = row[d];  // 0 past D and for padding rows
+    if (!cosine) return x;
+    return nrm > 0.f ? x / nrm : 0.f;  // correctly rounded division (HIP default)
+  };
+  int e = 0;
+  if (CDT == DT_FP8) {
+    float amax = 0.f;
+#pragma unroll
+    for (int j = 0; j < kMaxDpad / 64; ++j) {
+      const int d = 64 * j + lane;
+      if (d < D) amax = fmaxf(amax, fabsf(get(d)));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+    e = fp8_row_exponent(amax);
+  }
+  const float down = exp2i(-e);
+  constexpr int E = CDT == DT_F32 ? 4 : (CDT == DT_BF16 ? 8 : 16);  // elements per 16 bytes
+  unsigned char* tb = tiles + (r >> 5) * tile_bytes(ng);
+  const int rr = (int)(r & 31);
+  if (lane < 2 * ng) {
+    const int g = lane >> 1, hf = lane & 1;
+    const int d0 = g * 2 * E + hf * E;
+    u32x4 wv = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int d = d0 + k;
+      const float x = d < D ? get(d) : 0.f;
+      if (CDT == DT_F32) {
+        wv[k] = __float_as_uint(x);
+      } else if (CDT == DT_BF16) {
+        wv[k >> 1] |= bf16_rne(x) << (16 * (k & 1));
+      } else {
+        wv[k >> 2] |= fp8_e4m3_rne(x * down) << (8 * (k & 3));
+      }
+    }
+    *reinterpret_cast<u32x4*>(tb + piece_offset(rr, g, hf, ng)) = wv;
+  }
+  if (lane == 0) {
+    unsigned char* aux = tb + ng * 1024;
+    const int half = (rr >> 2) & 1, idx = 4 * (rr >> 3) + (rr & 3);
+    reinterpret_cast<float*>(aux)[half * 16 + idx] = 0.f;
+    aux[128 + rr] = (unsigned char)(e + 127);
+  }
+}
+
 template <int CDT>
 __global__ __launch_bounds__(64) void prepare_segments_kernel(const QSeg* segs, int nseg, int64_t total_rows,
                                                                int in_dt) {
@@ -214,6 +297,16 @@ hipError_t launch_prepare(const void* src, int in_dt, int64_t rows, int D, int m
   const int ng = groups_for(dpad_for(D, compute), compute);
   const int64_t n = n_tiles * kTileRows;
   if (n == 0) return hipSuccess;
+  if (!database && !orig_half_norm && !orig_rnorm) {  // query rows: one wave per row
+    const unsigned qgrid = (unsigned)ceil_div(n, kQPrepWaves);
+    if (compute == DT_F32)
+      prepare_queries_kernel<DT_F32><<<qgrid, 64 * kQPrepWaves, 0, s>>>(src, in_dt, rows, D, ng, metric, tiles, n);
+    else if (compute == DT_BF16)
+      prepare_queries_kernel<DT_BF16><<<qgrid, 64 * kQPrepWaves, 0, s>>>(src, in_dt, rows, D, ng, metric, tiles, n);
+    else
+      prepare_queries_kernel<DT_FP8><<<qgrid, 64 * kQPrepWaves, 0, s>>>(src, in_dt, rows, D, ng, metric, tiles, n);
+    return hipGetLastError();
+  }
   const unsigned grid = (unsigned)ceil_div(n, kPrepRows);
   const size_t lds = sizeof(float) * kPrepRows * (size_t)(D + 1);  // <= 65,792 bytes (D <= 256)
   {

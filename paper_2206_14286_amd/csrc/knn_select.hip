@@ -431,14 +431,24 @@ __global__ __launch_bounds__(256) void select_wave_few_kernel(const float* __res
                       unit_lo(A[r * ldv + c * es]))
                    : 0ull;
     }
-    // sort the lane's keys, largest first (insertion network over R registers)
+    // sort the lane's keys, largest first: a bitonic network over the R registers
+    // (R log2(R) (log2(R) + 1) / 4 compare-exchanges: 80 for R = 16, where an
+    // insertion network takes 120)
 #pragma unroll
-    for (int i = 1; i < R; ++i) {
+    for (int size = 2; size <= R; size <<= 1) {
 #pragma unroll
-      for (int j = i; j > 0; --j) {
-        const unsigned long long a = k[j - 1], b = k[j];
-        k[j - 1] = a > b ? a : b;
-        k[j] = a > b ? b : a;
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int j = i ^ stride;
+          if (j > i) {
+            const unsigned long long a = k[i], b = k[j];
+            const bool desc = (i & size) == 0;
+            const bool sw = desc ? (a < b) : (a > b);
+            k[i] = sw ? b : a;
+            k[j] = sw ? a : b;
+          }
+        }
       }
     }
     for (int e = 0; e < K; ++e) {
@@ -497,6 +507,7 @@ hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t
 #undef KNN_SELW
     return hipGetLastError();
   }
+
   const int64_t grid = rows < 65536 ? rows : 65536;
   select_kernel<<<(unsigned)grid, kSelThreads, 0, s>>>(V, A, rows, n, ldv, es, K, minimize ? 1 : 0, out_val,
                                                        out_idx, ldout, eo);

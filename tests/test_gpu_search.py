@@ -153,6 +153,50 @@ def test_prepared_rows_match_reference_quantisers(metric, compute):
         np.testing.assert_allclose(hn, ref, rtol=2e-6, atol=1e-30)
 
 
+def decode_query_tiles(buf, M, D, compute):
+    """Rows of a prepared query buffer (the piece layout of the distance kernel's tiles):
+    element codes (M x D) and the per-row FP8 scale exponents."""
+    es = {"fp32": 4, "bf16": 2, "fp8": 1}[compute]
+    dp = dpad_of(D, compute)
+    ng = dp * es // 32
+    tb = ng * 1024 + 256
+    E = 16 // es
+    raw = buf.cpu().numpy()
+    cdt = {"fp32": np.uint32, "bf16": np.uint16, "fp8": np.uint8}[compute]
+    codes = np.zeros((M, dp), cdt)
+    exps = np.zeros(M, np.int64)
+    for r in range(M):
+        t, rr = divmod(r, 32)
+        base = t * tb
+        for g in range(ng):
+            for hf in range(2):
+                o = base + (rr // 4) * ng * 128 + g * 128 + hf * 64 + (rr % 4) * 16
+                d0 = g * 2 * E + hf * E
+                codes[r, d0:d0 + E] = raw[o:o + 16].view(cdt)
+        exps[r] = int(raw[base + ng * 1024 + 128 + rr]) - 127
+    return codes[:, :D], exps
+
+
+@pytest.mark.parametrize("metric,compute", [(m, c) for m in ("mips", "l2", "cosine") for c in ("fp32", "bf16", "fp8")])
+def test_prepared_queries_match_reference_quantisers(metric, compute):
+    """The query rows the kernel reads are bit-identical to the oracle's quantisers."""
+    _log(f"prepare queries {metric} {compute}")
+    M, D = 77, 100
+    Q = datagen.normal(M, D, 6) * np.float32(2.0)
+    Q[5] = 0
+    db = knn.Database(to_dev(datagen.normal(64, D, 7)), metric, compute)
+    codes, exps = decode_query_tiles(db.prepare_queries(to_dev(Q)), M, D, compute)
+    Qn = oracle.normalize_rows_f32(Q) if metric == "cosine" else Q
+    if compute == "fp32":
+        np.testing.assert_array_equal(codes, Qn.view(np.uint32))
+    elif compute == "bf16":
+        np.testing.assert_array_equal(codes, oracle.bf16_round(Qn)[1])
+    else:
+        _, c, e = oracle.fp8_quantize_rows(Qn)
+        np.testing.assert_array_equal(exps, e)
+        np.testing.assert_array_equal(codes, c)
+
+
 def test_l2_integer_data_exact():
     """Integer data in [0, 255]: every FP32 (and BF16) partial sum is exact, so bins and
     top-K must equal the oracle's bit for bit, ties included (lowest row wins)."""
