@@ -643,17 +643,21 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   };
 
   // Everything after a tile's scores are folded into (nbv, nbu): the fast path,
-  // the one-boundary masked path and the row walk, bin flushes.
-  auto finish = [&](int t0, f32x16 (&acc_c)[NCB], float (&nbv)[NCB], unsigned (&nbu)[NCB]) {
+  // the one-boundary masked path and the row walk, bin flushes.  may_fast false: the
+  // caller has already taken the fast case (nbv, nbu are then not used or computed).
+  auto finish = [&](auto may_fast, int t0, f32x16 (&acc_c)[NCB], float (&nbv)[NCB], unsigned (&nbu)[NCB]) {
+    constexpr bool kMayBeFast = decltype(may_fast)::value;
     const unsigned gu0 = 2u * (unsigned)t0 + 1u;
     // materialise the update here, inside the region with the MFMAs, rather than
     // letting the compiler sink it into the (rarely not taken) fast branch below
+    if constexpr (kMayBeFast) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) asm volatile("" : "+v"(nbv[cb]), "+v"(nbu[cb]));
+      for (int cb = 0; cb < NCB; ++cb) asm volatile("" : "+v"(nbv[cb]), "+v"(nbu[cb]));
+    }
     const int lo = t0 > r0 ? t0 : r0;
     const int hi = (t0 + 32) < r1 ? (t0 + 32) : r1;
     const bool whole = lo == t0 && hi == t0 + 32;  // the tile lies inside the item's rows
-    const bool fast = whole && t0 + 32 <= cursor.next32;  // whole tile in the current bin
+    const bool fast = kMayBeFast && whole && t0 + 32 <= cursor.next32;  // whole tile in the current bin
     float obv[NCB];
     unsigned obu[NCB];
 #pragma unroll
@@ -830,15 +834,8 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
         if (t0 + 32 == cursor.next32) flush_all();  // the bin ends with this tile
         continue;
       }
-      float nbv[NCB];
-      unsigned nbu[NCB];
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        nbv[cb] = bv[cb];
-        nbu[cb] = bu[cb];
-      }
-      static_for<0, 2 * NCB>([&](auto pc) { unit_pair(pc, acc, nbv, nbu, gu0); });
-      finish(t0, acc, nbv, nbu);
+      // a tile at an item edge or a bin boundary: the masked path or the row walk
+      finish(std::false_type{}, t0, acc, bv, bu);
     }
   } else {
     // Software pipeline over the chunk's tiles.  Step t: the tile loads run S tiles
@@ -878,7 +875,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       read_tile<NG, kZ>(fr, buf(t + 1));
       __builtin_amdgcn_sched_barrier(0);
       mma_tile_interleaved<DT, NG, NCB>(acc_n, fr, bq, sb, [&](auto pc) { unit_pair(pc, acc_c, nbv, nbu, gu0); });
-      finish(t0, acc_c, nbv, nbu);
+      finish(std::true_type{}, t0, acc_c, nbv, nbu);
     };
     for (int t = t_first; t <= t_last; t += 2) {
       step(t, acc_a, acc_b);
