@@ -94,6 +94,47 @@ def test_approx_top_k_matches_oracle(case):
     np.testing.assert_array_equal(i.cpu().numpy(), oi)
 
 
+def _planted_rows(rows, n, seed):
+    """N(0, 1) rows whose entries in 16 runs of 64 spread evenly over the row are raised
+    by 100 above all others: a sample taken at those runs would overstate the row's top
+    (a case for any sampling shortcut in the select)."""
+    a = datagen.score_matrix(rows, n, seed, "normal")
+    for ch in range(16):
+        s0 = (n - 64) * ch // 15
+        a[:, s0:s0 + 64] += np.float32(100.0)
+    return a
+
+
+SELECT_CASES = [
+    # name, rows, n (= L: one candidate per bin), K, minimize, kind
+    ("long_normal_k512_min", 4, 8192, 512, True, "normal"),
+    ("long_normal_k64_65536", 3, 65536, 64, False, "normal"),
+    ("long_normal_k300", 5, 18750, 300, False, "normal"),
+    ("long_ties_ints_fallback_cap", 3, 40000, 10, False, "ints"),
+    ("long_ties_ints_k100", 4, 16384, 100, True, "ints"),
+    ("long_planted_fallback_count", 3, 18750, 300, False, "planted"),
+    ("long_above_max_n", 2, 65537, 50, False, "normal"),
+    ("long_min_n", 3, 4096, 200, False, "masked"),
+]
+
+
+@pytest.mark.parametrize("case", SELECT_CASES, ids=[c[0] for c in SELECT_CASES])
+def test_select_long_rows(case):
+    """Top-K over 4096..65537 candidates per row (the key-range select): K up to 512,
+    minimisation, thousands of exact ties, masked scores and a row whose evenly spread
+    runs hold its largest values, bit for bit against the oracle."""
+    name, rows, n, K, mn, kind = case
+    _log(f"select case {name}: rows={rows} n={n} K={K} min={mn} {kind}")
+    seed = 500 + SELECT_CASES.index(case)
+    a = _planted_rows(rows, n, seed) if kind == "planted" else datagen.score_matrix(rows, n, seed, kind)
+    dev = torch.from_numpy(a).to(DEV)
+    v, i = knn.approx_top_k(dev, K, minimize=mn, L=n)
+    torch.cuda.synchronize()
+    ov, oi = oracle.approx_top_k(a.astype(np.float64), K, n, minimize=mn)
+    _same(v.cpu().numpy(), ov)
+    np.testing.assert_array_equal(i.cpu().numpy(), oi)
+
+
 def test_approx_two_calls_and_min_wrapper():
     """Consecutive calls with different shapes on the same stream, and approx_min_k."""
     for rows, cols in ((64, 8192), (3, 1000)):
