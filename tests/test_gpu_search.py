@@ -70,6 +70,11 @@ CASES = [
     ("mips", 140, 1800, 192, 8, 55, "fp32"),       # FP32 depth 192
     ("l2", 300, 2000, 20, 10, 100, "bf16"),        # BF16 depth 32
     ("mips", 100, 2222, 128, 10, 70, "bf16"),      # BF16 depth 128, one column block
+    # fewer rows than one 32-row tile
+    ("mips", 10, 5, 16, 2, 3, "fp32"),
+    ("l2", 7, 31, 64, 5, 31, "bf16"),
+    ("cosine", 5, 1, 8, 1, 1, "fp8"),
+    ("mips", 40, 20, 100, 4, 7, "fp8"),
 ]
 
 
@@ -212,6 +217,22 @@ def test_l2_integer_data_exact():
         np.testing.assert_array_equal(bv.cpu().numpy().astype(np.float64), ora["bin_v"])
         np.testing.assert_array_equal(idx.cpu().numpy(), ora["top_i"])
         np.testing.assert_array_equal(vals.cpu().numpy().astype(np.float64), ora["top_v"])
+
+
+@pytest.mark.parametrize("metric", ["mips", "l2", "cosine"])
+def test_plain_search_entry_point_vs_oracle(metric):
+    """knn_search (FP32 inputs, the database prepared inside the call) against the oracle."""
+    M, N, D, K, L = 77, 5000, 96, 10, 250
+    _log(f"plain knn_search {metric}")
+    Q, X = make_inputs(metric, M, N, D, seed=91)
+    v, i = knn.search(to_dev(Q), to_dev(X), K, L, metric)
+    torch.cuda.synchronize()
+    Qq = oracle.quantize_like_library(Q, metric, "fp32")
+    Xq = oracle.quantize_like_library(X, metric, "fp32")
+    mo = "mips" if metric == "cosine" else metric
+    ora = oracle.search(Qq, Xq, mo, L, K, bins=True)
+    check_topk(Qq, Xq, mo, K, v.cpu().numpy(), i.cpu().numpy(), ora, dpad_of(D, "fp32"), u=U_BOUND["fp32"],
+               value_rtol=V_RTOL["fp32"])
 
 
 def test_plain_search_entry_point():
