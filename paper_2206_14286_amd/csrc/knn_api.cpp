@@ -173,6 +173,7 @@ struct GroupPlan {  // all batches against one database
   int64_t M = 0, L = 0, L_min = 0, bins_per_chunk = 0, n_qb = 0, n_chunks = 0, q_tiles_n = 0;
   int32_t ncb = 1, K_max = 1;
   bool tune = false;  // still to be tuned in knn_plan_setup
+  bool own = false;   // enough work items for a launch of its own (set_group_shape)
   unsigned char* q_tiles = nullptr;  // inside the bound workspace
   float* binV = nullptr;
   int32_t* binA = nullptr;
@@ -774,11 +775,19 @@ namespace {
 constexpr int kPlanBlocksPerXcd = 64;  // 2 resident workgroups on each of an XCD's 32 CUs
 constexpr int kPlanBlocks = 8 * kPlanBlocksPerXcd;
 
+// A group with at least this many (query block, chunk) items fills the GPU for several
+// rounds on its own: it runs as a launch of the distance kernel specialised for its
+// depth (e.g. three waves per SIMD at depth 128, where the persistent kernel, which
+// holds every depth's code, runs two), inside the same captured sequence.  Smaller
+// groups share the persistent launch, which balances them against one another.
+constexpr int64_t kOwnLaunchItems = 4 * kPlanBlocks;
+
 void set_group_shape(GroupPlan& g) {
   const int64_t QB = (int64_t)kWaves * 32 * g.ncb;
   g.n_qb = ceil_div(std::max<int64_t>(g.M, 1), QB);
   g.q_tiles_n = g.n_qb * QB / kTileRows;
   g.n_chunks = ceil_div(g.L, g.bins_per_chunk);
+  g.own = g.M > 0 && g.n_chunks * g.n_qb >= kOwnLaunchItems;
 }
 
 // the autotuner's candidates for one group: L at or above the L2-resident choice (a bin
@@ -862,7 +871,7 @@ std::vector<WorkItem> build_items(const std::vector<GroupPlan>& groups) {
   int64_t chunk_seq = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const GroupPlan& g = groups[gi];
-    if (g.M == 0) continue;
+    if (g.M == 0 || g.own) continue;  // own launch (run_plan)
     for (int64_t c = 0; c < g.n_chunks; ++c, ++chunk_seq) {
       auto& lst = per_xcd[chunk_seq % 8];
       for (int64_t qb = 0; qb < g.n_qb; ++qb) {
@@ -1021,20 +1030,8 @@ knn_status bind_plan(knn_plan* p, unsigned char* ws, hipStream_t s) {
   return KNN_OK;
 }
 
-knn_status run_plan(knn_plan* p, hipStream_t s) {
-  HIP_TRY(launch_prepare_segments(p->d_segs, p->n_segs, p->total_q_rows, p->q_dtype, p->compute, s),
-          "batched query preparation");
-  HIP_TRY(launch_fused_persistent(p->compute, p->d_groups, p->d_items, p->n_items, p->n_blocks, p->lds_bytes, s),
-          "persistent distance + bin-reduce kernel");
-  HIP_TRY(launch_select_rows(p->d_sel, p->n_sel_rows, p->max_K, s), "batched top-K select");
-  HIP_TRY(launch_resolve_rows(p->compute, p->d_sel, p->n_sel_rows, s), "batched resolve");
-  return KNN_OK;
-}
-
-// time one group alone with its current (ncb, L, bins_per_chunk): non-persistent
-// distance launch + top-K, best of 3, the queries prepared by the plan's own launch
-double time_group(knn_plan* p, size_t gi, hipStream_t s) {
-  const GroupPlan& g = p->groups[gi];
+// the distance launch of one group on its own (its queries prepared by the plan)
+FusedParams group_params(const knn_plan* p, const GroupPlan& g) {
   const knn_db* db = p->dbs[g.db];
   FusedParams fp{};
   fp.db_tiles = db->tiles;
@@ -1050,6 +1047,29 @@ double time_group(knn_plan* p, size_t gi, hipStream_t s) {
   fp.binV = g.binV;
   fp.binA = g.binA;
   fp.ldo = g.L;
+  return fp;
+}
+
+knn_status run_plan(knn_plan* p, hipStream_t s) {
+  HIP_TRY(launch_prepare_segments(p->d_segs, p->n_segs, p->total_q_rows, p->q_dtype, p->compute, s),
+          "batched query preparation");
+  for (const auto& g : p->groups)
+    if (g.own)
+      HIP_TRY(launch_fused(p->dbs[g.db]->compute, p->dbs[g.db]->ng, g.ncb, group_params(p, g), s),
+              "distance + bin-reduce kernel (one database group)");
+  HIP_TRY(launch_fused_persistent(p->compute, p->d_groups, p->d_items, p->n_items, p->n_blocks, p->lds_bytes, s),
+          "persistent distance + bin-reduce kernel");
+  HIP_TRY(launch_select_rows(p->d_sel, p->n_sel_rows, p->max_K, s), "batched top-K select");
+  HIP_TRY(launch_resolve_rows(p->compute, p->d_sel, p->n_sel_rows, s), "batched resolve");
+  return KNN_OK;
+}
+
+// time one group alone with its current (ncb, L, bins_per_chunk): non-persistent
+// distance launch + top-K, best of 3, the queries prepared by the plan's own launch
+double time_group(knn_plan* p, size_t gi, hipStream_t s) {
+  const GroupPlan& g = p->groups[gi];
+  const knn_db* db = p->dbs[g.db];
+  const FusedParams fp = group_params(p, g);
   hipEvent_t a, b;
   double best = 1e30;
   if (hipEventCreate(&a) != hipSuccess) return best;

@@ -85,6 +85,47 @@ def test_batched_equals_unbatched_and_replays_in_a_graph():
         _ = torch.randn(1000, device=DEV).sum().item()  # unrelated eager work between replays
 
 
+def test_batched_plan_with_a_large_group():
+    """A plan where one database's batches are large enough for a launch of their own
+    (5,000 queries x 176 one-bin chunks: 3,520 work items) next to small groups that
+    share the persistent launch: every batch equals its unbatched search, bit for bit,
+    also on graph replays, and the large group's batches match the oracle."""
+    shapes = [(60000, 128), (3000, 64), (4000, 96)]
+    Xs = [bf16_dev(datagen.normal(n, d, 300 + i)) for i, (n, d) in enumerate(shapes)]
+    dbs = [knn.Database(x, "mips", "bf16") for x in Xs]
+    spec = [(0, 2000, 10), (1, 7, 10), (0, 3000, 10), (2, 130, 5), (1, 65, 3)]
+    batches = [(bf16_dev(datagen.normal(m, shapes[d][1], 400 + b)), d, k) for b, (d, m, k) in enumerate(spec)]
+    plan = knn.BatchedPlan(dbs, batches, recall_target=0.95, tune=False)
+    info = plan.info()
+    _log("plan", info)
+    outs = plan.run()
+    torch.cuda.synchronize()
+    refs = _reference(dbs, batches, info["L"])
+    for (ov, oi), (rv, ri) in zip(outs, refs):
+        assert torch.equal(oi, ri)
+        assert torch.equal(ov, rv)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run()
+    for rep in range(2):
+        for ov, oi in outs:
+            ov.zero_()
+            oi.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (ov, oi), (rv, ri) in zip(outs, refs):
+            assert torch.equal(oi, ri), f"replay {rep}"
+            assert torch.equal(ov, rv), f"replay {rep}"
+    Xf = dbs[0].X.float().cpu().numpy()
+    for b in (0, 2):
+        Q, _, k = batches[b]
+        sel = np.arange(0, Q.shape[0], 97)
+        Qf = Q.float().cpu().numpy()[sel]
+        ora = oracle.search(Qf, Xf, "mips", info["L"][0], k, bins=True)
+        check_topk(Qf, Xf, "mips", k, outs[b][0].cpu().numpy()[sel], outs[b][1].cpu().numpy()[sel], ora, 128)
+
+
 def test_autotuner_writes_cache_and_keeps_results_valid():
     dbs, batches = _make_batched(seed=7)
     with tempfile.TemporaryDirectory() as td:
