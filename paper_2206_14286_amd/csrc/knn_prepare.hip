@@ -189,23 +189,24 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(const void* src, 
                    tiles, orig_half_norm, orig_rnorm);
 }
 
-// Query rows: one wave per row, so that a few queries do not leave one thread per row
-// doing all of its work serially.  Lane l holds elements l, l + 64, ... of the row; for
-// cosine lane 0 sums the squares in dimension order (the same single-rounding sum as
-// prepare_row), the FP8 row maximum is a wave reduction (a maximum in any order is
-// exact), and lane p < 2 NG converts and stores piece p.  Produces the same bytes as
-// prepare_row for a query row (no half norm, init 0).
-constexpr int kQPrepWaves = 4;
+// One wave per row, so that a few rows do not leave one thread per row doing all of
+// its work serially.  Lane l holds elements l, l + 64, ... of the row; the sums that
+// have an order (|x|^2 for cosine and the original-row norms, the L2 half norm of the
+// converted row) are taken by lane 0 in dimension order with one rounding per product
+// and per sum, as prepare_row takes them; the FP8 row maximum is a wave reduction (a
+// maximum in any order is exact), and lane p < 2 NG converts and stores piece p.
+// Produces the same bytes as prepare_row.
+constexpr int kWPrepWaves = 4;
 
 template <int CDT>
-__global__ __launch_bounds__(64 * kQPrepWaves) void prepare_queries_kernel(const void* src, int in_dt, int64_t rows,
-                                                                          int D, int ng, int metric,
-                                                                          unsigned char* tiles,
-                                                                          int64_t n_rows_padded) {
+__global__ __launch_bounds__(64 * kWPrepWaves) void prepare_rows_wave_kernel(
+    const void* src, int in_dt, int64_t rows, int D, int ng, int metric, int database, unsigned char* tiles,
+    int64_t n_rows_padded, float* orig_half_norm, float* orig_rnorm) {
 #pragma clang fp contract(off)
-  __shared__ float stage[kQPrepWaves][kMaxDpad];
+  __shared__ float stage[kWPrepWaves][kMaxDpad];
+  __shared__ float dq[kWPrepWaves][kMaxDpad];  // dequantised converted row (L2 database half norm)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t r = (int64_t)blockIdx.x * kQPrepWaves + w;
+  const int64_t r = (int64_t)blockIdx.x * kWPrepWaves + w;
   if (r >= n_rows_padded) return;
   const bool valid = src != nullptr && r < rows;
   float* row = stage[w];
@@ -218,12 +219,16 @@ __global__ __launch_bounds__(64 * kQPrepWaves) void prepare_queries_kernel(const
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const bool cosine = metric == MET_COSINE;
+  const bool need_ss = cosine || orig_half_norm != nullptr || orig_rnorm != nullptr;
   float nrm = 0.f;
-  if (cosine) {
+  if (need_ss) {
     float ss = 0.f;
     if (lane == 0)
       for (int d = 0; d < D; ++d) ss = ss + row[d] * row[d];
-    nrm = sqrtf(__shfl(ss, 0));  // correctly rounded square root (HIP default)
+    ss = __shfl(ss, 0);
+    nrm = sqrtf(ss);  // correctly rounded square root (HIP default)
+    if (lane == 0 && valid && orig_half_norm) orig_half_norm[r] = 0.5f * ss;
+    if (lane == 0 && valid && orig_rnorm) orig_rnorm[r] = nrm > 0.f ? 1.f / nrm : 0.f;
   }
   auto get = [&](int d) -> float {
     const float x = row[d];  // 0 past D and for padding rows
@@ -242,10 +247,11 @@ __global__ __launch_bounds__(64 * kQPrepWaves) void prepare_queries_kernel(const
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
     e = fp8_row_exponent(amax);
   }
-  const float down = exp2i(-e);
+  const float down = exp2i(-e), up = exp2i(e);
   constexpr int E = CDT == DT_F32 ? 4 : (CDT == DT_BF16 ? 8 : 16);  // elements per 16 bytes
   unsigned char* tb = tiles + (r >> 5) * tile_bytes(ng);
   const int rr = (int)(r & 31);
+  const bool half_norm = database != 0 && metric == MET_L2;
   if (lane < 2 * ng) {
     const int g = lane >> 1, hf = lane & 1;
     const int d0 = g * 2 * E + hf * E;
@@ -254,20 +260,35 @@ __global__ __launch_bounds__(64 * kQPrepWaves) void prepare_queries_kernel(const
     for (int k = 0; k < E; ++k) {
       const int d = d0 + k;
       const float x = d < D ? get(d) : 0.f;
+      float deq;
       if (CDT == DT_F32) {
         wv[k] = __float_as_uint(x);
+        deq = x;
       } else if (CDT == DT_BF16) {
-        wv[k >> 1] |= bf16_rne(x) << (16 * (k & 1));
+        const unsigned bits = bf16_rne(x);
+        wv[k >> 1] |= bits << (16 * (k & 1));
+        deq = __uint_as_float(bits << 16);
       } else {
-        wv[k >> 2] |= fp8_e4m3_rne(x * down) << (8 * (k & 3));
+        const unsigned bits = fp8_e4m3_rne(x * down);
+        wv[k >> 2] |= bits << (8 * (k & 3));
+        deq = fp8_e4m3_value(bits) * up;
       }
+      if (half_norm) dq[w][d] = deq;
     }
     *reinterpret_cast<u32x4*>(tb + piece_offset(rr, g, hf, ng)) = wv;
+  }
+  float hh = 0.f;
+  if (half_norm) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0)
+      for (int d = 0; d < 2 * ng * E; ++d) hh = hh + dq[w][d] * dq[w][d];
   }
   if (lane == 0) {
     unsigned char* aux = tb + ng * 1024;
     const int half = (rr >> 2) & 1, idx = 4 * (rr >> 3) + (rr & 3);
-    reinterpret_cast<float*>(aux)[half * 16 + idx] = 0.f;
+    reinterpret_cast<float*>(aux)[half * 16 + idx] = half_norm ? -0.5f * hh : 0.f;
     aux[128 + rr] = (unsigned char)(e + 127);
   }
 }
@@ -297,14 +318,22 @@ hipError_t launch_prepare(const void* src, int in_dt, int64_t rows, int D, int m
   const int ng = groups_for(dpad_for(D, compute), compute);
   const int64_t n = n_tiles * kTileRows;
   if (n == 0) return hipSuccess;
-  if (!database && !orig_half_norm && !orig_rnorm) {  // query rows: one wave per row
-    const unsigned qgrid = (unsigned)ceil_div(n, kQPrepWaves);
+  // One wave per row for queries, and for database rows that need no ordered sum (MIPS
+  // without original-row norms): measured 2.74 -> 1.98 ms for 4M x 256 BF16 rows.  Rows
+  // whose half norm or cosine norm is summed in order keep one thread per row: lane 0
+  // of a wave summing alone is slower there (1M x 128 L2: 0.28 -> 0.74 ms).
+  if (!database || (metric == MET_MIPS && !orig_half_norm && !orig_rnorm)) {
+    const unsigned wgrid = (unsigned)ceil_div(n, kWPrepWaves);
+    const int db = database ? 1 : 0;
     if (compute == DT_F32)
-      prepare_queries_kernel<DT_F32><<<qgrid, 64 * kQPrepWaves, 0, s>>>(src, in_dt, rows, D, ng, metric, tiles, n);
+      prepare_rows_wave_kernel<DT_F32><<<wgrid, 64 * kWPrepWaves, 0, s>>>(src, in_dt, rows, D, ng, metric, db, tiles, n,
+                                                                         orig_half_norm, orig_rnorm);
     else if (compute == DT_BF16)
-      prepare_queries_kernel<DT_BF16><<<qgrid, 64 * kQPrepWaves, 0, s>>>(src, in_dt, rows, D, ng, metric, tiles, n);
+      prepare_rows_wave_kernel<DT_BF16><<<wgrid, 64 * kWPrepWaves, 0, s>>>(src, in_dt, rows, D, ng, metric, db, tiles,
+                                                                          n, orig_half_norm, orig_rnorm);
     else
-      prepare_queries_kernel<DT_FP8><<<qgrid, 64 * kQPrepWaves, 0, s>>>(src, in_dt, rows, D, ng, metric, tiles, n);
+      prepare_rows_wave_kernel<DT_FP8><<<wgrid, 64 * kWPrepWaves, 0, s>>>(src, in_dt, rows, D, ng, metric, db, tiles, n,
+                                                                         orig_half_norm, orig_rnorm);
     return hipGetLastError();
   }
   const unsigned grid = (unsigned)ceil_div(n, kPrepRows);
