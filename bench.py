@@ -287,7 +287,9 @@ def row_cosine_glove(torch, knn, datagen, oracle, steps, warmup, sample_n=256):
 def row_batched(torch, knn, datagen, steps):
     """256 query batches (log-uniform sizes in [1, 4096]) against four BF16 databases in one
     persistent launch, replayed from a captured graph; the plan from the fixed heuristic and
-    the plan the autotuner picks (it times candidate L and chunk sizes per database).
+    the plan the autotuner picks (it times candidate L and chunk sizes per database).  Beside
+    them (not the row's figure): the heuristic plan with own launches for database groups of
+    at least 2,048 work items (knn_plan_set_own_launches).
     Roofline: per database the larger of its MFMA time and one read of its rows, summed."""
     bf16 = torch.bfloat16
     xs = [datagen.normal_device(n, d, seed=1000 + i, dtype=bf16) for i, (n, d) in enumerate(datagen.BATCHED_DBS)]
@@ -306,9 +308,9 @@ def row_batched(torch, knn, datagen, steps):
     nq = int(sizes.sum())
     out = {"workload": "batched", "batches": len(sizes), "queries": nq, "databases": datagen.BATCHED_DBS,
            "roofline_bound_ms": bound * 1e3}
-    for name, tune in (("heuristic", False), ("autotuned", True)):
+    for name, tune, own in (("heuristic", False, 0), ("autotuned", True, 0), ("own_launches", False, 2048)):
         t0 = time.perf_counter()
-        plan = knn.BatchedPlan(dbs, batches, recall_target=0.95, tune=tune)
+        plan = knn.BatchedPlan(dbs, batches, recall_target=0.95, tune=tune, own_launch_min_items=own)
         create_s = time.perf_counter() - t0
         plan.run()
         torch.cuda.synchronize()

@@ -253,6 +253,15 @@ knn_status knn_plan_setup(knn_plan* plan, void* workspace, size_t ws_bytes, void
  * captured into a hipGraph.  KNN_ERR_INVALID before knn_plan_setup. */
 knn_status knn_search_batched(knn_plan* plan, void* stream);
 
+/* Scheduling option (not in the paper): database groups with at least `min_items`
+ * (query block, chunk) work items run as distance launches of their own, with the
+ * kernel specialised for their depth, before the persistent launch that the smaller
+ * groups share (all of it still one capturable sequence on one stream).  0, the
+ * default, keeps every group in the one persistent launch.  Host only; takes effect at
+ * the next knn_plan_setup (the plan must be set up again).  KNN_ERR_INVALID for a NULL
+ * plan or min_items < 0. */
+knn_status knn_plan_set_own_launches(knn_plan* plan, int64_t min_items);
+
 /* The plan's per-database choices: L, query-block width and rows per work item
  * (host arrays of length ndb; any may be NULL). */
 knn_status knn_plan_info(const knn_plan* plan, int64_t* L, int32_t* qblock, int64_t* chunk_rows);

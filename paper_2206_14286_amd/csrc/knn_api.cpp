@@ -173,7 +173,7 @@ struct GroupPlan {  // all batches against one database
   int64_t M = 0, L = 0, L_min = 0, bins_per_chunk = 0, n_qb = 0, n_chunks = 0, q_tiles_n = 0;
   int32_t ncb = 1, K_max = 1;
   bool tune = false;  // still to be tuned in knn_plan_setup
-  bool own = false;   // enough work items for a launch of its own (set_group_shape)
+  bool own = false;   // runs as a launch of its own (bind_plan; knn_plan_set_own_launches)
   unsigned char* q_tiles = nullptr;  // inside the bound workspace
   float* binV = nullptr;
   int32_t* binA = nullptr;
@@ -187,6 +187,7 @@ struct knn_plan {
   std::string cache_path;
   int64_t total_q_rows = 0, n_items = 0, n_sel_rows = 0;
   int n_blocks = 0, max_ng = 0, n_segs = 0, max_K = 1, lds_bytes = 0;
+  int64_t own_launch_items = 0;  // groups with this many work items launch alone (0: never)
   bool bound = false;  // knn_plan_setup succeeded
   // descriptors: built on the host, uploaded into the workspace
   std::vector<QSeg> segs;
@@ -775,19 +776,20 @@ namespace {
 constexpr int kPlanBlocksPerXcd = 64;  // 2 resident workgroups on each of an XCD's 32 CUs
 constexpr int kPlanBlocks = 8 * kPlanBlocksPerXcd;
 
-// A group with at least this many (query block, chunk) items fills the GPU for several
-// rounds on its own: it runs as a launch of the distance kernel specialised for its
-// depth (e.g. three waves per SIMD at depth 128, where the persistent kernel, which
-// holds every depth's code, runs two), inside the same captured sequence.  Smaller
-// groups share the persistent launch, which balances them against one another.
-constexpr int64_t kOwnLaunchItems = 4 * kPlanBlocks;
-
 void set_group_shape(GroupPlan& g) {
   const int64_t QB = (int64_t)kWaves * 32 * g.ncb;
   g.n_qb = ceil_div(std::max<int64_t>(g.M, 1), QB);
   g.q_tiles_n = g.n_qb * QB / kTileRows;
   g.n_chunks = ceil_div(g.L, g.bins_per_chunk);
-  g.own = g.M > 0 && g.n_chunks * g.n_qb >= kOwnLaunchItems;
+}
+
+// With knn_plan_set_own_launches: a group with enough (query block, chunk) items to
+// fill the GPU for several rounds runs as a launch of the distance kernel specialised
+// for its depth (e.g. three waves per SIMD at depth 128, where the persistent kernel,
+// which holds every depth's code, runs two).  The others share the persistent launch,
+// which balances them against one another.
+void set_own_launch(const knn_plan* p, GroupPlan& g) {
+  g.own = p->own_launch_items > 0 && g.M > 0 && g.n_chunks * g.n_qb >= p->own_launch_items;
 }
 
 // the autotuner's candidates for one group: L at or above the L2-resident choice (a bin
@@ -928,7 +930,10 @@ size_t plan_bound_bytes(const knn_plan* p) {
 
 // Lay out the plan's current choices in the workspace and upload its descriptors.
 knn_status bind_plan(knn_plan* p, unsigned char* ws, hipStream_t s) {
-  for (auto& g : p->groups) set_group_shape(g);
+  for (auto& g : p->groups) {
+    set_group_shape(g);
+    set_own_launch(p, g);
+  }
   p->items = build_items(p->groups);
   const PlanLayout lay = plan_layout(p, p->groups, items_bound(p));
   p->segs.clear();
@@ -1284,6 +1289,15 @@ extern "C" knn_status knn_search_batched(knn_plan* plan, void* stream) {
   if (!plan) return fail(KNN_ERR_INVALID, "plan is NULL");
   if (!plan->bound) return fail(KNN_ERR_INVALID, "plan has no workspace: call knn_plan_setup first");
   return run_plan(plan, (hipStream_t)stream);
+}
+
+extern "C" knn_status knn_plan_set_own_launches(knn_plan* plan, int64_t min_items) {
+  g_last_error.clear();
+  if (!plan) return fail(KNN_ERR_INVALID, "plan is NULL");
+  if (min_items < 0) return fail(KNN_ERR_INVALID, "min_items must be >= 0 (got %lld)", (long long)min_items);
+  plan->own_launch_items = min_items;
+  plan->bound = false;  // the work list changes: knn_plan_setup again
+  return KNN_OK;
 }
 
 extern "C" knn_status knn_plan_info(const knn_plan* plan, int64_t* L, int32_t* qblock, int64_t* chunk_rows) {

@@ -65,6 +65,7 @@ def lib():
             "knn_plan_setup": (i32, [P, P, SZ, P]),
             "knn_search_batched": (i32, [P, P]),
             "knn_plan_info": (i32, [P, P, P, P]),
+            "knn_plan_set_own_launches": (i32, [P, i64]),
             "knn_plan_destroy": (i32, [P]),
             "knn_backward": (i32, [P, P, P, P, i32, i64, i64, i32, i32, i32, P, P, P]),
             "knn_query_buffer_bytes": (SZ, [P, i64]),
@@ -279,8 +280,11 @@ class BatchedPlan:
     """``knn_plan_create`` / ``knn_plan_setup`` / ``knn_search_batched`` over several prepared
     databases; the plan's workspace is a torch allocation this object owns."""
 
-    def __init__(self, dbs, batches, recall_target: float = 0.95, tune: bool = False, cache_path: str | None = None):
-        """batches: list of (Q tensor, db index, k).  Output tensors are allocated here and bound to the plan."""
+    def __init__(self, dbs, batches, recall_target: float = 0.95, tune: bool = False, cache_path: str | None = None,
+                 own_launch_min_items: int = 0):
+        """batches: list of (Q tensor, db index, k).  Output tensors are allocated here and bound to the plan.
+        own_launch_min_items > 0: ``knn_plan_set_own_launches`` (database groups with at least that many
+        work items get a distance launch of their own; 0 keeps one persistent launch)."""
         self.dbs = list(dbs)
         self.outs = []
         arr = (KnnBatch * len(batches))()
@@ -306,6 +310,8 @@ class BatchedPlan:
         _check(lib().knn_plan_create(hs, len(self.dbs), arr, len(batches), qdt, float(recall_target), int(tune),
                                      cache_path.encode() if cache_path else None, ctypes.byref(h)))
         self._h = h
+        if own_launch_min_items:
+            _check(lib().knn_plan_set_own_launches(self._h, int(own_launch_min_items)))
         n = ctypes.c_size_t()
         _check(lib().knn_plan_workspace_size(self._h, ctypes.byref(n)))
         self.workspace = _device_buffer(n.value, self.dbs[0].X.device)

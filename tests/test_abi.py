@@ -160,3 +160,4 @@ def test_plan_create_is_host_only_and_checks_arguments(K):
     assert lib.knn_plan_create(hs, 1, arr, 1, 1, 0.95, 0, None, ctypes.byref(out)) == 1  # NULL database
     assert b"database 0 is NULL" in lib.knn_last_error()
     assert lib.knn_plan_workspace_size(None, ctypes.byref(ctypes.c_size_t())) == 1
+    assert lib.knn_plan_set_own_launches(None, 2048) == 1

@@ -86,16 +86,17 @@ def test_batched_equals_unbatched_and_replays_in_a_graph():
 
 
 def test_batched_plan_with_a_large_group():
-    """A plan where one database's batches are large enough for a launch of their own
-    (5,000 queries x 176 one-bin chunks: 3,520 work items) next to small groups that
-    share the persistent launch: every batch equals its unbatched search, bit for bit,
-    also on graph replays, and the large group's batches match the oracle."""
+    """With own launches for groups of at least 2,048 work items, a plan where one
+    database's batches qualify (5,000 queries x 176 one-bin chunks: 3,520 items) next to
+    small groups that share the persistent launch: every batch equals its unbatched
+    search, bit for bit, also on graph replays, and the large group's batches match the
+    oracle."""
     shapes = [(60000, 128), (3000, 64), (4000, 96)]
     Xs = [bf16_dev(datagen.normal(n, d, 300 + i)) for i, (n, d) in enumerate(shapes)]
     dbs = [knn.Database(x, "mips", "bf16") for x in Xs]
     spec = [(0, 2000, 10), (1, 7, 10), (0, 3000, 10), (2, 130, 5), (1, 65, 3)]
     batches = [(bf16_dev(datagen.normal(m, shapes[d][1], 400 + b)), d, k) for b, (d, m, k) in enumerate(spec)]
-    plan = knn.BatchedPlan(dbs, batches, recall_target=0.95, tune=False)
+    plan = knn.BatchedPlan(dbs, batches, recall_target=0.95, tune=False, own_launch_min_items=2048)
     info = plan.info()
     _log("plan", info)
     outs = plan.run()
