@@ -1008,6 +1008,7 @@ knn_status bind_plan(knn_plan* p, unsigned char* ws, hipStream_t s) {
     gd.ldo = g.L;
     gd.ng = db->ng;
     gd.ncb = g.ncb;
+    gd.zero_init = db->metric != KNN_L2;
     p->gds.push_back(gd);
   }
   p->total_q_rows = first;

@@ -949,9 +949,9 @@ hipError_t launch_one(const FusedParams& p, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- persistent batched form
-template <int DT, int NG, int NCB>
+template <int DT, int NG, int NCB, bool kZ>
 __device__ __forceinline__ void run_group_item(const GroupDesc& gd, const WorkItem& it, unsigned char* lds) {
-  run_item<DT, NG, NCB, false, false, false>(gd.db_tiles, gd.q_tiles, gd.N, gd.L, gd.M, (int64_t)it.qb * (kWaves * 32 * NCB), it.b0,
+  run_item<DT, NG, NCB, false, kZ, false>(gd.db_tiles, gd.q_tiles, gd.N, gd.L, gd.M, (int64_t)it.qb * (kWaves * 32 * NCB), it.b0,
                         it.b1, gd.out_sign, gd.binV, gd.binA, gd.ldo, lds);
 }
 
@@ -968,14 +968,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
     __syncthreads();  // the previous item's LDS use is over
     switch (gd.ng * 4 + gd.ncb) {
       // BF16 depths 64, 96, 128, 256 (NG = 4, 6, 8, 16) and FP32 / FP8 equivalents
-      case 4 * 4 + 1: run_group_item<DT, 4, 1>(gd, it, lds); break;
-      case 4 * 4 + 2: run_group_item<DT, 4, 2>(gd, it, lds); break;
-      case 6 * 4 + 1: run_group_item<DT, 6, 1>(gd, it, lds); break;
-      case 6 * 4 + 2: run_group_item<DT, 6, 2>(gd, it, lds); break;
-      case 8 * 4 + 1: run_group_item<DT, 8, 1>(gd, it, lds); break;
-      case 8 * 4 + 2: run_group_item<DT, 8, 2>(gd, it, lds); break;
-      case 16 * 4 + 1: run_group_item<DT, 16, 1>(gd, it, lds); break;
-      case 16 * 4 + 2: run_group_item<DT, 16, 2>(gd, it, lds); break;
+      case 4 * 4 + 1:
+        if (gd.zero_init) run_group_item<DT, 4, 1, true>(gd, it, lds); else run_group_item<DT, 4, 1, false>(gd, it, lds);
+        break;
+      case 4 * 4 + 2:
+        if (gd.zero_init) run_group_item<DT, 4, 2, true>(gd, it, lds); else run_group_item<DT, 4, 2, false>(gd, it, lds);
+        break;
+      case 6 * 4 + 1:
+        if (gd.zero_init) run_group_item<DT, 6, 1, true>(gd, it, lds); else run_group_item<DT, 6, 1, false>(gd, it, lds);
+        break;
+      case 6 * 4 + 2:
+        if (gd.zero_init) run_group_item<DT, 6, 2, true>(gd, it, lds); else run_group_item<DT, 6, 2, false>(gd, it, lds);
+        break;
+      case 8 * 4 + 1:
+        if (gd.zero_init) run_group_item<DT, 8, 1, true>(gd, it, lds); else run_group_item<DT, 8, 1, false>(gd, it, lds);
+        break;
+      case 8 * 4 + 2:
+        if (gd.zero_init) run_group_item<DT, 8, 2, true>(gd, it, lds); else run_group_item<DT, 8, 2, false>(gd, it, lds);
+        break;
+      case 16 * 4 + 1:
+        if (gd.zero_init) run_group_item<DT, 16, 1, true>(gd, it, lds); else run_group_item<DT, 16, 1, false>(gd, it, lds);
+        break;
+      case 16 * 4 + 2:
+        if (gd.zero_init) run_group_item<DT, 16, 2, true>(gd, it, lds); else run_group_item<DT, 16, 2, false>(gd, it, lds);
+        break;
       default: break;
     }
   }

@@ -109,6 +109,7 @@ struct GroupDesc {     // all queries against one database, concatenated
   int32_t* binA;
   int64_t ldo;
   int32_t ng, ncb;
+  int32_t zero_init, pad_;  // as FusedParams::zero_init
 };
 // lds_bytes_needed: the largest fused_lds_bytes() over the groups the items touch
 hipError_t launch_fused_persistent(int dt, const GroupDesc* d_groups, const WorkItem* d_items, int64_t n_items,
