@@ -89,9 +89,17 @@ constexpr int win_bins() {
   return (DT == DT_FP8 && NG == 4 && !kS) ? 8 : 16;
 }
 
-template <int DT, int NG, bool kS = false>
+// Depth split (kSplit, at most 64 queries: one column block for each of two waves):
+// waves 0-1 and 2-3 take the two halves of each tile's depth for the same queries, so
+// all four SIMDs of a CU do matrix work; the second pair hands its partial sums to the
+// first through two LDS buffers of 2 x 64 lanes x 16 floats.
+constexpr int kXchgBytes = 2 * 2 * 64 * 16 * 4;
+
+// (output windows for the waves that hold bins: all four, or the first pair when split)
+template <int DT, int NG, bool kS = false, bool kSplit = false>
 constexpr int lds_bytes() {
-  return stages<DT, NG, kS>() * TileGeom<NG>::kLdsBytes + kWaves * stage_words<win_bins<DT, NG, kS>()>() * 4;
+  return stages<DT, NG, kS>() * TileGeom<NG>::kLdsBytes +
+         (kSplit ? 2 : kWaves) * stage_words<win_bins<DT, NG, kS>()>() * 4 + (kSplit ? kXchgBytes : 0);
 }
 
 // wait until at most N vector-memory loads of this wave are outstanding
@@ -184,8 +192,8 @@ struct TileRegs {
 };
 
 // kZ: the accumulators start from zero (MIPS, cosine): the start values are not read
-// and the first matrix instruction takes an inline zero
-template <int NG, bool kZ>
+// and the first matrix instruction takes an inline zero.  Groups [G0, G0 + NGP) only.
+template <int NG, bool kZ, int G0 = 0, int NGP = NG>
 __device__ __forceinline__ void read_tile(TileRegs<NG>& r, const unsigned char* tile) {
   using G = TileGeom<NG>;
   const int lane = threadIdx.x & 63, h = lane >> 5;
@@ -203,7 +211,7 @@ __device__ __forceinline__ void read_tile(TileRegs<NG>& r, const unsigned char* 
   const int base = rg * NG * 128 + (q & 3) * 16 + ((h << 6) ^ (sw & 64));
   const int a_even = base + (sw & 128), a_odd = base - (sw & 128);  // (g ^ b7) * 128 = g * 128 +- b7 * 128
 #pragma unroll
-  for (int g = 0; g < NG; ++g)
+  for (int g = G0; g < G0 + NGP; ++g)
     r.af[g] = *reinterpret_cast<const u32x4*>(tile + ((g & 1) ? a_odd : a_even) + g * 128);
 }
 
@@ -268,31 +276,33 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-template <int DT, int NG, int NCB, class UnitFn>
+// Groups [G0, G0 + NGP) of the depth only (the depth-split form).
+template <int DT, int NG, int NCB, int G0 = 0, int NGP = NG, class UnitFn>
 __device__ __forceinline__ void mma_tile_interleaved(f32x16 (&acc)[NCB], const TileRegs<NG>& r,
                                                      const u32x4 (&bq)[NCB][NG], const int (&sb)[NCB],
                                                      UnitFn&& unit) {
-  constexpr int P = DT == DT_FP8 ? NG / 2 : (DT == DT_BF16 ? NG : 4 * NG);  // k-steps per column block
+  static_assert(G0 % 2 == 0 && NGP % 2 == 0 && G0 + NGP <= NG, "group range");
+  constexpr int P = DT == DT_FP8 ? NGP / 2 : (DT == DT_BF16 ? NGP : 4 * NGP);  // k-steps per column block
   constexpr int U = 4 * NCB;
   static_for<0, P>([&](auto sc) {
     constexpr int s = decltype(sc)::value;
     static_for<0, NCB>([&](auto cc) {
       constexpr int cb = decltype(cc)::value;
       if constexpr (DT == DT_FP8) {
-        const u32x4& a0 = r.af[2 * s];
-        const u32x4& a1 = r.af[2 * s + 1];
-        const u32x4& b0 = bq[cb][2 * s];
-        const u32x4& b1 = bq[cb][2 * s + 1];
+        const u32x4& a0 = r.af[G0 + 2 * s];
+        const u32x4& a1 = r.af[G0 + 2 * s + 1];
+        const u32x4& b0 = bq[cb][G0 + 2 * s];
+        const u32x4& b1 = bq[cb][G0 + 2 * s + 1];
         i32x8 A = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
         i32x8 B = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
         acc[cb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, B, s == 0 ? r.init : acc[cb], 0, 0, 0, r.sa, 0,
                                                                    sb[cb]);
       } else if constexpr (DT == DT_BF16) {
-        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, r.af[s]),
-                                                          __builtin_bit_cast(bf16x8, bq[cb][s]),
+        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, r.af[G0 + s]),
+                                                          __builtin_bit_cast(bf16x8, bq[cb][G0 + s]),
                                                           s == 0 ? r.init : acc[cb], 0, 0, 0);
       } else {
-        constexpr int g = s >> 2, e = s & 3;
+        constexpr int g = G0 + (s >> 2), e = s & 3;
         acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(r.af[g][e]), __uint_as_float(bq[cb][g][e]),
                                                        s == 0 ? r.init : acc[cb], 0, 0, 0);
       }
@@ -530,8 +540,9 @@ __device__ __forceinline__ BinCursor make_cursor(int64_t b, int64_t N, int64_t L
 }
 
 // kPrio: raise the wave priority while a wave issues a tile's matrix instructions
-// (pays off with three waves per SIMD, costs with two)
-template <int DT, int NG, int NCB, bool kPrio, bool kZ, bool kS>
+// (pays off with three waves per SIMD, costs with two).  kSplit: the depth-split form
+// (see kXchgBytes): a query block of 64 queries.
+template <int DT, int NG, int NCB, bool kPrio, bool kZ, bool kS, bool kSplit = false>
 __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_tiles,
                                          const unsigned char* __restrict__ q_tiles, int64_t N, int64_t L, int64_t M,
                                          int64_t q0, int64_t b0, int64_t b1, float sign, float* __restrict__ outV,
@@ -543,8 +554,17 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
   const int h = lane >> 5, ql = lane & 31;
+  static_assert(!kSplit || (NCB == 1 && !kSingleAcc<DT, NG>() && NG % 4 == 0), "depth split: one column block");
+  // depth split: waves 2-3 compute depth groups [NG/2, NG) for the queries of waves 0-1
+  const int part = kSplit ? (wave >> 1) : 0, qwave = kSplit ? (wave & 1) : wave;
+  constexpr int NGP = kSplit ? NG / 2 : NG;
   constexpr int W = win_bins<DT, NG, kS>();
-  float* stage = reinterpret_cast<float*>(lds + S * G::kLdsBytes) + wave * stage_words<W>();
+  // output window of the wave (split: only the first pair holds bins)
+  float* stage = reinterpret_cast<float*>(lds + S * G::kLdsBytes) + qwave * stage_words<W>();
+  // the exchange buffer of tile t: float4 i of lane l at [(t & 1) * 2 + qwave][i][l]
+  float4* const xchg =
+      reinterpret_cast<float4*>(lds + S * G::kLdsBytes + (kSplit ? 2 : kWaves) * stage_words<W>() * 4) +
+      qwave * 4 * 64 + lane;
   // widest store the output rows allow (window starts are multiples of 4 bins)
   const uintptr_t oaddr = reinterpret_cast<uintptr_t>(outV) | reinterpret_cast<uintptr_t>(outA);
   const int vec_ok = ((oaddr & 15) == 0 && (ldo & 3) == 0) ? 4 : (((oaddr & 7) == 0 && (ldo & 1) == 0) ? 2 : 1);
@@ -556,7 +576,7 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
   auto buf = [&](int t) { return lds + ((t - t_first) & (S - 1)) * G::kLdsBytes; };
 
   // query fragments of this wave (tiles of 32 queries; the buffer is padded)
-  const int64_t wq0 = q0 + (int64_t)wave * 32 * NCB;
+  const int64_t wq0 = q0 + (int64_t)qwave * 32 * NCB;
   u32x4 bq[NCB][NG];
   int sb[NCB];
 #pragma unroll
@@ -873,11 +893,45 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       if (t_first + s <= t_last) load_tile<NG>(db_tiles + (int64_t)(t_first + s) * TB, lds + s * G::kLdsBytes, plan, wave, lane);
     TileRegs<NG> fr;
     f32x16 acc_a[NCB], acc_b[NCB];
+    // depth split: the second wave pair's sums of tile t, handed over through LDS (the
+    // step's barrier orders the write before the read; a buffer is rewritten two steps on)
+    auto put_partial = [&](const f32x16& a, int t) {
+      float4* x = xchg + (t & 1) * 2 * 4 * 64;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i * 64] = make_float4(a[4 * i], a[4 * i + 1], a[4 * i + 2], a[4 * i + 3]);
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // written before the next barrier
+    };
+    auto add_partial = [&](f32x16& a, int t) {
+      const float4* x = xchg + (t & 1) * 2 * 4 * 64;
+      float4 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = x[i * 64];
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // read before the next barrier
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[4 * i] += v[i].x;
+        a[4 * i + 1] += v[i].y;
+        a[4 * i + 2] += v[i].z;
+        a[4 * i + 3] += v[i].w;
+      }
+    };
+    auto no_units = [](auto) {};
     if (t_last - t_first >= S - 1) wait_vmcnt<(S - 1) * G::kLoads>(); else wait_vmcnt<0>();
     lds_barrier();
     if (active) {
-      read_tile<NG, kZ>(fr, buf(t_first));
-      mma_tile<DT, NG, NCB>(acc_a, fr, bq, sb);
+      if constexpr (kSplit) {
+        if (part == 0) {
+          read_tile<NG, kZ, 0, NGP>(fr, buf(t_first));
+          mma_tile_interleaved<DT, NG, NCB, 0, NGP>(acc_a, fr, bq, sb, no_units);
+        } else {
+          read_tile<NG, true, NGP, NGP>(fr, buf(t_first));
+          mma_tile_interleaved<DT, NG, NCB, NGP, NGP>(acc_a, fr, bq, sb, no_units);
+          put_partial(acc_a[0], t_first);
+        }
+      } else {
+        read_tile<NG, kZ>(fr, buf(t_first));
+        mma_tile<DT, NG, NCB>(acc_a, fr, bq, sb);
+      }
     }
     auto step = [&](int t, f32x16 (&acc_c)[NCB], f32x16 (&acc_n)[NCB]) {
       if (t + 1 <= t_last) {
@@ -888,6 +942,15 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
       // tile t's fragments were read in the previous step: its buffer takes tile t+S
       if (t + S <= t_last) load_tile<NG>(db_tiles + (int64_t)(t + S) * TB, buf(t), plan, wave, lane);
       if (!active) return;
+      if constexpr (kSplit) {
+        if (part == 1) {  // the second half of tile t+1's depth, handed to waves 0-1
+          read_tile<NG, true, NGP, NGP>(fr, buf(t + 1));
+          mma_tile_interleaved<DT, NG, NCB, NGP, NGP>(acc_n, fr, bq, sb, no_units);
+          put_partial(acc_n[0], t + 1);
+          return;
+        }
+        add_partial(acc_c[0], t);
+      }
       const int t0 = t << 5;
       const unsigned gu0 = 2u * (unsigned)t0 + 1u;  // lane-local unit of accumulator group 0 (uniform)
       float nbv[NCB];
@@ -897,9 +960,9 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
         nbv[cb] = bv[cb];
         nbu[cb] = bu[cb];
       }
-      read_tile<NG, kZ>(fr, buf(t + 1));
+      read_tile<NG, kZ, 0, NGP>(fr, buf(t + 1));
       __builtin_amdgcn_sched_barrier(0);
-      mma_tile_interleaved<DT, NG, NCB>(acc_n, fr, bq, sb, [&](auto pc) { unit_pair(pc, acc_c, nbv, nbu, gu0); });
+      mma_tile_interleaved<DT, NG, NCB, 0, NGP>(acc_n, fr, bq, sb, [&](auto pc) { unit_pair(pc, acc_c, nbv, nbu, gu0); });
       finish(std::true_type{}, t0, acc_c, nbv, nbu);
     };
     for (int t = t_first; t <= t_last; t += 2) {
@@ -919,7 +982,7 @@ constexpr int min_waves() {
   return (DT == DT_FP8 && NG == 4) ? (kS ? 3 : 4) : (((DT == DT_FP8 && NG < 4) || (DT == DT_BF16 && NG == 8)) ? 3 : 1);
 }
 
-template <int DT, int NG, int NCB, bool kZ, bool kS>
+template <int DT, int NG, int NCB, bool kZ, bool kS, bool kSplit = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<DT, NG, kS>(), 8)))
 void fused_kernel(FusedParams p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -930,21 +993,23 @@ void fused_kernel(FusedParams p) {
   if (chunk >= p.n_chunks) return;
   const int64_t b0 = chunk * p.bins_per_chunk;
   const int64_t b1 = (b0 + p.bins_per_chunk) < p.L ? (b0 + p.bins_per_chunk) : p.L;
-  run_item<DT, NG, NCB, (min_waves<DT, NG, kS>() >= 3), kZ, kS>(p.db_tiles, p.q_tiles, p.N, p.L, p.M, (int64_t)qb * (kWaves * 32 * NCB), b0, b1, p.out_sign, p.binV,
-                        p.binA, p.ldo, lds);
+  constexpr int64_t QB = (kSplit ? 2 : kWaves) * 32 * NCB;  // queries per block
+  run_item<DT, NG, NCB, (min_waves<DT, NG, kS>() >= 3), kZ, kS, kSplit>(p.db_tiles, p.q_tiles, p.N, p.L, p.M, (int64_t)qb * QB,
+                                                                         b0, b1, p.out_sign, p.binV, p.binA, p.ldo, lds);
 }
 
-template <int DT, int NG, int NCB, bool kZ, bool kS>
+template <int DT, int NG, int NCB, bool kZ, bool kS, bool kSplit = false>
 hipError_t launch_one(const FusedParams& p, hipStream_t s) {
   (void)hipGetLastError();  // clear any stale error so the check below sees this launch only
   const int64_t per_xcd = ceil_div(p.n_chunks, 8);
   const int64_t grid = 8 * per_xcd * p.n_qb;
-  constexpr int lb = lds_bytes<DT, NG, kS>();
+  constexpr int lb = lds_bytes<DT, NG, kS, kSplit>();
   {
-    const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&fused_kernel<DT, NG, NCB, kZ, kS>), lb);
+    const hipError_t e =
+        ensure_dynamic_lds(reinterpret_cast<const void*>(&fused_kernel<DT, NG, NCB, kZ, kS, kSplit>), lb);
     if (e != hipSuccess) return e;
   }
-  fused_kernel<DT, NG, NCB, kZ, kS><<<dim3((unsigned)grid), dim3(64 * kWaves), lb, s>>>(p);
+  fused_kernel<DT, NG, NCB, kZ, kS, kSplit><<<dim3((unsigned)grid), dim3(64 * kWaves), lb, s>>>(p);
   return hipGetLastError();
 }
 
@@ -1037,6 +1102,13 @@ bool fused_supported(int dt, int ng, int ncb) {
 
 hipError_t launch_fused(int dt, int ng, int ncb, const FusedParams& p, hipStream_t s) {
   if (p.M == 0 || p.n_chunks == 0) return hipSuccess;
+  if (dt == DT_F32 && ncb == 1 && p.M <= 64) {  // one query block of at most 64 queries: depth split
+#define X(G_)        \
+  if (ng == G_)      \
+    return p.zero_init ? launch_one<DT_F32, G_, 1, true, false, true>(p, s) : launch_one<DT_F32, G_, 1, false, false, true>(p, s);
+    X(4) X(8) X(12) X(16) X(24) X(32)
+#undef X
+  }
   if (dt == DT_FP8 && ng == 4 && p.N <= 128 * p.L) {  // bins of at most 128 rows
     if (ncb == 2)
       return p.zero_init ? launch_one<DT_FP8, 4, 2, true, true>(p, s) : launch_one<DT_FP8, 4, 2, false, true>(p, s);

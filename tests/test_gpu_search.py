@@ -70,6 +70,11 @@ CASES = [
     ("mips", 140, 1800, 192, 8, 55, "fp32"),       # FP32 depth 192
     ("l2", 300, 2000, 20, 10, 100, "bf16"),        # BF16 depth 32
     ("mips", 100, 2222, 128, 10, 70, "bf16"),      # BF16 depth 128, one column block
+    # at most 64 queries in FP32: the depth-split kernel (two wave pairs per query block)
+    ("l2", 48, 3001, 256, 10, 100, "fp32"),        # depth 256, bins of 30-31 rows, ragged tail tile
+    ("l2", 64, 2000, 96, 5, 37, "fp32"),           # depth 96, bins of 54-55 rows: one boundary per tile
+    ("cosine", 20, 1500, 192, 6, 15, "fp32"),      # depth 192, one query wave, bins of 100 rows
+    ("mips", 64, 4096, 64, 8, 16, "fp32"),         # depth 64, bins of 256 rows
     # fewer rows than one 32-row tile
     ("mips", 10, 5, 16, 2, 3, "fp32"),
     ("l2", 7, 31, 64, 5, 31, "bf16"),
@@ -209,14 +214,15 @@ def test_l2_integer_data_exact():
     Q = datagen.int_mixture(M, D, 31)
     X = datagen.int_mixture(N, D, 30)
     ora = oracle.search(Q, X, "l2", L, K, bins=True)
-    for compute in ("fp32", "bf16"):
-        _log(f"l2 exact {compute}")
+    # 48 queries: the FP32 search takes the depth-split kernel (partial sums added in LDS)
+    for compute, m in (("fp32", M), ("bf16", M), ("fp32", 48)):
+        _log(f"l2 exact {compute} M={m}")
         db = knn.Database(to_dev(X), "l2", compute)
-        vals, idx, bv, bi = db.search(to_dev(Q), K, L, return_bins=True)
-        np.testing.assert_array_equal(bi.cpu().numpy(), ora["bin_i"])
-        np.testing.assert_array_equal(bv.cpu().numpy().astype(np.float64), ora["bin_v"])
-        np.testing.assert_array_equal(idx.cpu().numpy(), ora["top_i"])
-        np.testing.assert_array_equal(vals.cpu().numpy().astype(np.float64), ora["top_v"])
+        vals, idx, bv, bi = db.search(to_dev(Q[:m]), K, L, return_bins=True)
+        np.testing.assert_array_equal(bi.cpu().numpy(), ora["bin_i"][:m])
+        np.testing.assert_array_equal(bv.cpu().numpy().astype(np.float64), ora["bin_v"][:m])
+        np.testing.assert_array_equal(idx.cpu().numpy(), ora["top_i"][:m])
+        np.testing.assert_array_equal(vals.cpu().numpy().astype(np.float64), ora["top_v"][:m])
 
 
 @pytest.mark.parametrize("metric", ["mips", "l2", "cosine"])
