@@ -190,8 +190,13 @@ __device__ void select_row(SelShared& sh, const float* __restrict__ V, const int
 // of them complete the K.  Three reads of the row instead of five or more; when b*
 // holds more than kRangeCap candidates (a dense cluster of equal-looking scores) the
 // row falls back to the byte-wise radix select.
-constexpr int kRangeBuckets = 2048;
-constexpr int kRangeCap = 2048;
+// Sized for occupancy: 16 KB of LDS and <= 64 VGPRs give eight workgroups per CU, which
+// the passes (latency-bound: each wave waits on its loads) need more than finer buckets
+// or more loads in flight per thread (cosine FP8, 10,000 rows of 18,750: 2048 buckets, a
+// 2048-key tie buffer, 8 loads per thread at 4 waves/SIMD 3.72 ms per search; these
+// settings 3.40 ms).
+constexpr int kRangeBuckets = 1024;
+constexpr int kRangeCap = 512;
 
 struct RangeShared {
   unsigned hist[kRangeBuckets];
@@ -228,11 +233,12 @@ __device__ __forceinline__ void bitonic_desc_lds(unsigned long long* a, int m) {
   }
 }
 
-// f(c, key) for every candidate c of the row, the keys of kSelThreads * 8 candidates
-// loaded before any is used (enough bytes in flight to stream the row)
+// f(c, key) for every candidate c of the row, the keys of kSelThreads * 4 candidates
+// loaded before any is used (more per thread costs registers and occupancy: 8 and 16
+// were slower)
 template <class F>
 __device__ __forceinline__ void for_each_key(const float* __restrict__ V, int64_t n, int64_t es, float sgn, F f) {
-  constexpr int U = 8;
+  constexpr int U = 4;
   for (int64_t c0 = threadIdx.x; c0 < n; c0 += (int64_t)kSelThreads * U) {
     float v[U];
 #pragma unroll
@@ -286,7 +292,7 @@ __device__ void select_row_any(SelUnion& u, const float* __restrict__ V, const i
   // pass 2: histogram over the range
   for_each_key(V, n, es, sgn, [&](int64_t, unsigned k) { atomicAdd(&r.hist[(k - kmin) >> shift], 1u); });
   __syncthreads();
-  if (tid < 64) {  // one wave: lane l sums buckets [B - 32(l+1), B - 32l), top first
+  if (tid < 64) {  // one wave: lane l sums buckets [B - PER(l+1), B - PER l), top first
     constexpr int PER = kRangeBuckets / 64;
     unsigned sum = 0;
 #pragma unroll 8
@@ -355,7 +361,7 @@ __device__ void select_row_any(SelUnion& u, const float* __restrict__ V, const i
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kSelThreads) void select_kernel(const float* __restrict__ V,
+__global__ __launch_bounds__(kSelThreads) __attribute__((amdgpu_waves_per_eu(8, 10))) void select_kernel(const float* __restrict__ V,
                                                              const int32_t* __restrict__ A, int64_t rows, int64_t n,
                                                              int64_t ldv, int64_t es, int K, int minimize,
                                                              float* __restrict__ out_val,
@@ -367,7 +373,7 @@ __global__ __launch_bounds__(kSelThreads) void select_kernel(const float* __rest
                    out_idx + r * ldout, eo);
 }
 
-__global__ __launch_bounds__(kSelThreads) void select_rows_kernel(const SelRow* __restrict__ rows_desc,
+__global__ __launch_bounds__(kSelThreads) __attribute__((amdgpu_waves_per_eu(8, 10))) void select_rows_kernel(const SelRow* __restrict__ rows_desc,
                                                                   int64_t rows) {
   __shared__ SelUnion sh;
   for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
