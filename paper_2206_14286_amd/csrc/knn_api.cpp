@@ -197,6 +197,7 @@ struct knn_plan {
   QSeg* d_segs = nullptr;
   GroupDesc* d_groups = nullptr;
   WorkItem* d_items = nullptr;
+  unsigned* d_claim = nullptr;  // the persistent kernel's 8 per-XCD item counters
   SelRow* d_sel = nullptr;
   float* tune_val = nullptr;  // autotuner's top-K output
   int32_t* tune_idx = nullptr;
@@ -826,7 +827,7 @@ std::vector<GroupPlan> tune_candidates(const knn_plan* p, const GroupPlan& g) {
 // many items instead of the current ones.
 struct PlanLayout {
   std::vector<size_t> q, bv, ba;
-  size_t segs = 0, gds = 0, items = 0, sel = 0, tv = 0, ti = 0, total = 0;
+  size_t segs = 0, gds = 0, items = 0, claim = 0, sel = 0, tv = 0, ti = 0, total = 0;
 };
 
 int64_t count_sel_rows(const knn_plan* p) {
@@ -855,6 +856,8 @@ PlanLayout plan_layout(const knn_plan* p, const std::vector<GroupPlan>& groups, 
   off += align_up(sizeof(GroupDesc) * (groups.size() + 1));
   l.items = off;
   off += align_up(sizeof(WorkItem) * (size_t)std::max<int64_t>(1, n_items));
+  l.claim = off;
+  off += align_up(sizeof(unsigned) * 8);
   l.sel = off;
   off += align_up(sizeof(SelRow) * (size_t)std::max<int64_t>(1, count_sel_rows(p)));
   l.tv = off;
@@ -867,7 +870,8 @@ PlanLayout plan_layout(const knn_plan* p, const std::vector<GroupPlan>& groups, 
 
 // work list: chunks dealt round-robin to the 8 XCDs; the items of one chunk (all its
 // query blocks) are consecutive in that XCD's list, so the persistent workgroups of one
-// XCD share a chunk's tiles through its L2.  Padded to whole rounds of kPlanBlocks.
+// XCD, which take the list in order, share a chunk's tiles through its L2.  The 8 lists
+// are stored one after another, each padded to the longest.
 std::vector<WorkItem> build_items(const std::vector<GroupPlan>& groups) {
   std::vector<std::vector<WorkItem>> per_xcd(8);
   int64_t chunk_seq = 0;
@@ -886,18 +890,12 @@ std::vector<WorkItem> build_items(const std::vector<GroupPlan>& groups) {
       }
     }
   }
-  size_t rounds = 0;
-  for (auto& l : per_xcd) rounds = std::max<size_t>(rounds, (size_t)ceil_div((int64_t)l.size(), kPlanBlocksPerXcd));
-  std::vector<WorkItem> items(rounds * kPlanBlocks);
-  for (size_t r = 0; r < rounds; ++r)
-    for (int w = 0; w < kPlanBlocks; ++w) {
-      const int x = w % 8, i = w / 8;
-      const size_t k = r * kPlanBlocksPerXcd + i;
-      WorkItem it{};
-      it.grp = -1;
-      if (k < per_xcd[x].size()) it = per_xcd[x][k];
-      items[r * kPlanBlocks + w] = it;
-    }
+  size_t len = 0;
+  for (auto& l : per_xcd) len = std::max(len, l.size());
+  WorkItem pad{};
+  pad.grp = -1;
+  std::vector<WorkItem> items(8 * len, pad);
+  for (int x = 0; x < 8; ++x) std::copy(per_xcd[x].begin(), per_xcd[x].end(), items.begin() + (size_t)x * len);
   return items;
 }
 
@@ -1019,6 +1017,7 @@ knn_status bind_plan(knn_plan* p, unsigned char* ws, hipStream_t s) {
   p->d_segs = reinterpret_cast<QSeg*>(ws + lay.segs);
   p->d_groups = reinterpret_cast<GroupDesc*>(ws + lay.gds);
   p->d_items = reinterpret_cast<WorkItem*>(ws + lay.items);
+  p->d_claim = reinterpret_cast<unsigned*>(ws + lay.claim);
   p->d_sel = reinterpret_cast<SelRow*>(ws + lay.sel);
   p->tune_val = reinterpret_cast<float*>(ws + lay.tv);
   p->tune_idx = reinterpret_cast<int32_t*>(ws + lay.ti);
@@ -1063,7 +1062,8 @@ knn_status run_plan(knn_plan* p, hipStream_t s) {
     if (g.own)
       HIP_TRY(launch_fused(p->dbs[g.db]->compute, p->dbs[g.db]->ng, g.ncb, group_params(p, g), s),
               "distance + bin-reduce kernel (one database group)");
-  HIP_TRY(launch_fused_persistent(p->compute, p->d_groups, p->d_items, p->n_items, p->n_blocks, p->lds_bytes, s),
+  HIP_TRY(launch_fused_persistent(p->compute, p->d_groups, p->d_items, p->n_items, p->d_claim, p->n_blocks,
+                                  p->lds_bytes, s),
           "persistent distance + bin-reduce kernel");
   HIP_TRY(launch_select_rows(p->d_sel, p->n_sel_rows, p->max_K, s), "batched top-K select");
   HIP_TRY(launch_resolve_rows(p->compute, p->d_sel, p->n_sel_rows, s), "batched resolve");

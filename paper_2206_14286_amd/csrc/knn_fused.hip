@@ -1014,6 +1014,11 @@ hipError_t launch_one(const FusedParams& p, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- persistent batched form
+// the 8 per-XCD item counters start from zero at every launch
+__global__ __launch_bounds__(64) void reset_claims_kernel(unsigned* __restrict__ claim) {
+  if (threadIdx.x < 8) claim[threadIdx.x] = 0u;
+}
+
 template <int DT, int NG, int NCB, bool kZ>
 __device__ __forceinline__ void run_group_item(const GroupDesc& gd, const WorkItem& it, unsigned char* lds) {
   run_item<DT, NG, NCB, false, kZ, false>(gd.db_tiles, gd.q_tiles, gd.N, gd.L, gd.M, (int64_t)it.qb * (kWaves * 32 * NCB), it.b0,
@@ -1021,16 +1026,29 @@ __device__ __forceinline__ void run_group_item(const GroupDesc& gd, const WorkIt
 }
 
 // Held to 2 waves per SIMD (<= 256 VGPRs): with every depth's case inlined the
-// compiler would otherwise size the registers for all of them at once.
+// compiler would otherwise size the registers for all of them at once.  Items are
+// claimed in list order per XCD (a counter bumped by one lane per workgroup), so the
+// workgroups running at any moment on an XCD hold neighbouring items, i.e. the query
+// blocks of one chunk, and share its tiles in L2 (striding through the list by the
+// grid size lets them drift apart).
 template <int DT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void fused_persistent_kernel(
-    const GroupDesc* __restrict__ groups, const WorkItem* __restrict__ items, int64_t n_items) {
+    const GroupDesc* __restrict__ groups, const WorkItem* __restrict__ items, int64_t n_items,
+    unsigned* __restrict__ claim) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  for (int64_t w = blockIdx.x; w < n_items; w += gridDim.x) {
-    const WorkItem it = items[w];
+  __shared__ unsigned next_item;
+  const int xcd = blockIdx.x & 7;
+  const int64_t per_xcd = n_items / 8;
+  const WorkItem* list = items + xcd * per_xcd;
+  for (;;) {
+    __syncthreads();  // the previous item's LDS use and every read of next_item are over
+    if (threadIdx.x == 0) next_item = atomicAdd(&claim[xcd], 1u);
+    __syncthreads();
+    const int64_t k = next_item;
+    if (k >= per_xcd) break;  // uniform
+    const WorkItem it = list[k];
     if (it.grp < 0) continue;  // padding slot of the per-XCD work lists
     const GroupDesc gd = groups[it.grp];
-    __syncthreads();  // the previous item's LDS use is over
     switch (gd.ng * 4 + gd.ncb) {
       // BF16 depths 64, 96, 128, 256 (NG = 4, 6, 8, 16) and FP32 / FP8 equivalents
       case 4 * 4 + 1:
@@ -1124,16 +1142,18 @@ hipError_t launch_fused(int dt, int ng, int ncb, const FusedParams& p, hipStream
 }
 
 hipError_t launch_fused_persistent(int dt, const GroupDesc* d_groups, const WorkItem* d_items, int64_t n_items,
-                                   int n_blocks, int lds_bytes_needed, hipStream_t s) {
+                                   unsigned* d_claim, int n_blocks, int lds_bytes_needed, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
   if (dt != DT_BF16) return hipErrorInvalidValue;  // the batched form is built for BF16 databases
+  if (n_items % 8 != 0 || n_items / 8 >= (int64_t(1) << 31) || n_blocks % 8 != 0) return hipErrorInvalidValue;
   const int lb = lds_bytes_needed;
   (void)hipGetLastError();
   {
     const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&fused_persistent_kernel<DT_BF16>), lb);
     if (e != hipSuccess) return e;
   }
-  fused_persistent_kernel<DT_BF16><<<n_blocks, 64 * kWaves, lb, s>>>(d_groups, d_items, n_items);
+  reset_claims_kernel<<<1, 64, 0, s>>>(d_claim);
+  fused_persistent_kernel<DT_BF16><<<n_blocks, 64 * kWaves, lb, s>>>(d_groups, d_items, n_items, d_claim);
   return hipGetLastError();
 }
 

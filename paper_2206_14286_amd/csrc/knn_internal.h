@@ -111,9 +111,12 @@ struct GroupDesc {     // all queries against one database, concatenated
   int32_t ng, ncb;
   int32_t zero_init, pad_;  // as FusedParams::zero_init
 };
-// lds_bytes_needed: the largest fused_lds_bytes() over the groups the items touch
+// The items are 8 lists of n_items / 8, one per XCD (workgroup b runs on XCD b % 8);
+// the workgroups of an XCD take its items in list order through the counter
+// claim[xcd], which the launch resets first (a kernel, not a memset: graph-safe).
+// lds_bytes_needed: the largest fused_lds_bytes() over the groups the items touch.
 hipError_t launch_fused_persistent(int dt, const GroupDesc* d_groups, const WorkItem* d_items, int64_t n_items,
-                                   int n_blocks, int lds_bytes_needed, hipStream_t s);
+                                   unsigned* d_claim, int n_blocks, int lds_bytes_needed, hipStream_t s);
 
 // Raise a kernel's dynamic LDS limit to at least `bytes` on the current device (once
 // per kernel, device and size; function attributes are per device).
