@@ -247,10 +247,13 @@ knn_status knn_plan_create(knn_db* const* dbs, int32_t ndb, const knn_batch* bat
 knn_status knn_plan_workspace_size(const knn_plan* plan, size_t* bytes);
 knn_status knn_plan_setup(knn_plan* plan, void* workspace, size_t ws_bytes, void* stream);
 
-/* Run every batch of the plan: one query-preparation launch, one persistent
- * distance + bin-reduce launch over a device work list that covers all batches
- * and databases, and one top-K launch.  No allocation, no host synchronisation: may be
- * captured into a hipGraph.  KNN_ERR_INVALID before knn_plan_setup. */
+/* Run every batch of the plan: one query-preparation launch, a one-workgroup launch
+ * that zeroes the persistent kernel's 8 item counters (held in the workspace), one
+ * persistent distance + bin-reduce launch over a device work list that covers all
+ * batches and databases, one top-K launch and one launch that resolves the winners'
+ * rows.  No allocation, no memset, no host synchronisation: may be captured into a
+ * hipGraph.  Runs on one stream at a time (the counters and bins are the plan's).
+ * KNN_ERR_INVALID before knn_plan_setup. */
 knn_status knn_search_batched(knn_plan* plan, void* stream);
 
 /* Scheduling option (not in the paper): database groups with at least `min_items`
