@@ -77,6 +77,53 @@ __device__ __forceinline__ void resolve16(int32_t* p, const unsigned char* __res
   const unsigned char* qtile = q_tiles + (qrow >> 5) * TB;
   const int qq = (int)(qrow & 31);
   const float* init = reinterpret_cast<const float*>(dtile + ng * 1024);
+  if (2 * ng <= 8) {
+    // Rows of at most 8 pieces (FP8 depth <= 128, BF16 <= 64, FP32 <= 32): the two 8-lane
+    // halves take alternate blocks (half hb: blocks hb, hb + 2), one piece per lane, an
+    // 8-lane butterfly (the same sums as the 16-lane one, whose upper lanes would add
+    // zeros), then the halves merge by larger value, then lower row: the row a scan in
+    // increasing row order with a strict compare keeps.
+    const int hb = gl >> 3, g8 = gl & 7;
+    float hv = -INFINITY;
+    int hbest = -1;  // row within the tile
+    for (int blk = hb; blk < nblk; blk += 2) {
+      const int r0 = (int)(first & 31) + blk * step;
+      float dot[4] = {0.f, 0.f, 0.f, 0.f};
+      if (g8 < 2 * ng) {
+        const int g = g8 >> 1, hf = g8 & 1;
+        const u32x4 b = *reinterpret_cast<const u32x4*>(qtile + piece_offset(qq, g, hf, ng));
+        const unsigned char* a = dtile + piece_offset(r0, g, hf, ng);
+        u32x4 ar[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ar[r] = *reinterpret_cast<const u32x4*>(a + r * 16);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dot[r] = piece_dot<DT>(ar[r], b, dot[r]);
+      }
+#pragma unroll
+      for (int off = 4; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dot[r] += __shfl_xor(dot[r], off, 8);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = r0 + r;
+        float d = dot[r];
+        if constexpr (DT == DT_FP8) {
+          const int ea = (int)dtile[ng * 1024 + 128 + rr] - 127, eb = (int)qtile[ng * 1024 + 128 + qq] - 127;
+          d = d * exp2i(ea) * exp2i(eb);
+        }
+        const float v = init[((rr >> 2) & 1) * 16 + 4 * (rr >> 3) + (rr & 3)] + d;
+        if (hbest < 0 || v > hv) {
+          hv = v;
+          hbest = rr;
+        }
+      }
+    }
+    const float ov = __shfl_xor(hv, 8, 16);
+    const int ob = __shfl_xor(hbest, 8, 16);
+    if (ob >= 0 && (hbest < 0 || ov > hv || (ov == hv && ob < hbest))) hbest = ob;
+    if (gl == 0) *p = (int32_t)((first & ~(int64_t)31) + hbest);
+    return;
+  }
   float bv = -INFINITY;
   int64_t best = first;
   for (int blk = 0; blk < nblk; ++blk) {
