@@ -872,12 +872,14 @@ __device__ __forceinline__ void run_item(const unsigned char* __restrict__ db_ti
 #pragma unroll
       for (int s2 = 0; s2 < S - 1; ++s2)
         if (t_first + s2 <= t_last) load_tile<NG>(db_tiles + (int64_t)(t_first + s2) * TB, lds + s2 * G::kLdsBytes, plan, wave, lane);
-      for (int t = t_first; t <= t_last; ++t) {
+      // the next tile to load, advanced by one tile per step (no per-step multiply)
+      const unsigned char* src = db_tiles + (int64_t)(t_first + S - 1) * TB;
+      for (int t = t_first; t <= t_last; ++t, src += TB) {
         // tiles issued so far: up to min(t + S - 2, t_last); tile t has landed once the
         // later ones are the only loads pending
         if (t_last - t >= S - 2) wait_vmcnt<(S - 2) * G::kLoads>(); else wait_vmcnt<0>();
         lds_barrier();
-        if (t + S - 1 <= t_last) load_tile<NG>(db_tiles + (int64_t)(t + S - 1) * TB, buf(t + S - 1), plan, wave, lane);
+        if (t + S - 1 <= t_last) load_tile<NG>(src, buf(t + S - 1), plan, wave, lane);
         if (!active) continue;
         tile_step(t);
       }
