@@ -444,13 +444,15 @@ __device__ __forceinline__ void merge_halves(float v, unsigned u, int h, float& 
 
 // bins output: value in the metric's sign; a row r >= 0; -2 - s/4 for a group,
 // -2 - 2^29 - s/4 for a pair, -2 - 2^30 - s/16 for a quad starting at row s; -1 when
-// the bin saw no finite score
+// the bin saw no finite score.  Every form computed, then selected: as a chain of early
+// returns it compiles to divergent branches at every bin flush.
 __device__ __forceinline__ int32_t bin_code(unsigned u) {
-  if (u == kNoUnit) return -1;
-  if (!(u & 1u)) return (int32_t)(u >> 1);
-  if ((u & 7u) == 1u) return -2 - (int32_t)(u >> 3);
-  if ((u & 7u) == 3u) return -2 - (1 << 29) - (int32_t)(u >> 3);
-  return -2 - (1 << 30) - (int32_t)(u >> 5);
+  const int32_t row = (int32_t)(u >> 1), s3 = (int32_t)(u >> 3);
+  const int32_t group = -2 - s3, pair = -2 - (1 << 29) - s3, quad = -2 - (1 << 30) - (int32_t)(u >> 5);
+  const unsigned t = u & 7u;
+  const int32_t odd = t == 1u ? group : (t == 3u ? pair : quad);
+  const int32_t c = (u & 1u) ? odd : row;
+  return u == kNoUnit ? -1 : c;
 }
 
 // put one query's finished bin into the wave's output window
