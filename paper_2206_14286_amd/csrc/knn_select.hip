@@ -488,7 +488,11 @@ hipError_t launch_select(const float* V, const int32_t* A, int64_t rows, int64_t
   (void)hipGetLastError();  // report only this call's launch errors
   if (rows == 0) return hipSuccess;
   if (K > kMaxK || K < 1 || n < 1) return hipErrorInvalidValue;
-  if (n <= 1024) {  // short rows: a wave per row, sorted in registers
+  // short rows: a wave per row, sorted in registers; K > 32 over more than 256
+  // candidates takes the key-range select instead (the register sort of 512-1024 keys
+  // needs 111-209 VGPRs, 2-4 waves per SIMD: FP8 search, L = 704, K_r = 100, 1.52 ->
+  // 1.41 ms per step)
+  if (n <= 1024 && (K <= 32 || n <= 256)) {
     const int64_t want = ceil_div(rows, 4);
     const unsigned grid = (unsigned)(want < 65536 ? want : 65536);
     const int nn = (int)n, mz = minimize ? 1 : 0;
