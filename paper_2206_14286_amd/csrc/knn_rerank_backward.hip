@@ -28,10 +28,12 @@ __device__ __forceinline__ float wave_sum(float v) {
 // row and split its depth into 16-byte pieces (4 FP32 or 8 BF16 elements per lane
 // per pass); a fixed 16-lane butterfly sums the pieces.  Keys (score, lower index
 // first on ties) go through the wave's LDS slots into a register bitonic sort.
-template <int R>
+// XDT: the original rows' type (FP32 or BF16), fixed per instance so that an FP32
+// instance holds 4 query elements per piece, not 8
+template <int R, int XDT>
 __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(const int32_t* __restrict__ cand, int64_t M, int Kr,
                                                                 const void* __restrict__ Q, int q_dt,
-                                                                const void* __restrict__ X, int x_dt, int D,
+                                                                const void* __restrict__ X, int D,
                                                                 int metric, const float* __restrict__ x_half_norm,
                                                                 const float* __restrict__ x_rnorm, int K,
                                                                 float* __restrict__ out_val,
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(const int32_t* _
   __shared__ unsigned long long slots[kRerankThreads / 64][64 * R];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane >> 4, gl = lane & 15;
-  const int E = x_dt == DT_F32 ? 4 : 8;  // elements per 16-byte piece
+  constexpr int E = XDT == DT_F32 ? 4 : 8;  // elements per 16-byte piece
   const int per_pass = 16 * E;
   const int passes = (D + per_pass - 1) / per_pass;  // <= 4 for D <= 256
   // whole 16-byte pieces when every row starts 16-byte aligned
@@ -47,13 +49,13 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(const int32_t* _
   unsigned long long* key_slot = slots[wave];
   for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < M; i += (int64_t)gridDim.x * 4) {
     // this lane's query elements, in the order its pieces cover the depth
-    float q[4][8];
+    float q[4][E];
 #pragma unroll
     for (int ps = 0; ps < 4; ++ps)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < E; ++e) {
         const int d = ps * per_pass + gl * E + e;
-        q[ps][e] = (ps < passes && e < E && d < D) ? load_elem(Q, q_dt, i * D + d) : 0.f;
+        q[ps][e] = (ps < passes && d < D) ? load_elem(Q, q_dt, i * D + d) : 0.f;
       }
     float rq = 1.f;
     if (metric == MET_COSINE) {
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(kRerankThreads) void rerank_kernel(const int32_t* _
             if (ps >= passes) break;
             const int d0 = ps * per_pass + gl * E;
             if (d0 < D) {
-              if (x_dt == DT_F32) {
+              if constexpr (XDT == DT_F32) {
                 const float* xr = reinterpret_cast<const float*>(X) + (int64_t)j * D + d0;
                 if (vec) {
                   const float4 v = *reinterpret_cast<const float4*>(xr);
@@ -253,9 +255,15 @@ hipError_t launch_rerank(const int32_t* cand, int64_t M, int Kr, const void* Q, 
   if (Kr > kRerankMaxKr || K > Kr || D > 256) return hipErrorInvalidValue;
   const int64_t want = ceil_div(M, 4);
   const unsigned grid = (unsigned)(want < 16384 ? want : 16384);
-#define KNN_RERANK(R_)                                                                                             \
-  rerank_kernel<R_><<<grid, kRerankThreads, 0, s>>>(cand, M, Kr, Q, q_dt, X, x_dt, D, metric, x_half_norm, x_rnorm, \
-                                                    K, out_val, out_idx)
+#define KNN_RERANK(R_)                                                                                        \
+  do {                                                                                                        \
+    if (x_dt == DT_F32)                                                                                       \
+      rerank_kernel<R_, DT_F32><<<grid, kRerankThreads, 0, s>>>(cand, M, Kr, Q, q_dt, X, D, metric, x_half_norm, \
+                                                                x_rnorm, K, out_val, out_idx);                  \
+    else                                                                                                      \
+      rerank_kernel<R_, DT_BF16><<<grid, kRerankThreads, 0, s>>>(cand, M, Kr, Q, q_dt, X, D, metric,            \
+                                                                 x_half_norm, x_rnorm, K, out_val, out_idx);    \
+  } while (0)
   if (Kr <= 64)
     KNN_RERANK(1);
   else if (Kr <= 128)
